@@ -1,0 +1,140 @@
+/*
+ * dpo — nested-parallel BFS and SSSP on MI355X (gfx950) with thresholding,
+ * coarsening and multi-block-granularity aggregation.
+ *
+ * Method: "A Compiler Framework for Optimizing Dynamic Parallelism on GPUs"
+ * (arXiv 2201.02789).  A parent thread per frontier vertex owns the child
+ * work of its neighbours (Sec. II-A).  The three transformations of the paper
+ * are applied by hand in the kernels:
+ *   thresholding (Sec. III-B): a parent whose child-thread count (its degree,
+ *     Sec. III-D) is below T runs the child work serially itself;
+ *   coarsening (Sec. IV-B): one child block runs CF original child blocks;
+ *   aggregation (Sec. II-B, V-A): the child grids of a wave, a block or a
+ *     group of k blocks are fused into one grid whose blocks find their parent
+ *     by a binary search of the scanned grid sizes.
+ * HIP has no device-side grid launch, so a "launch" is a device-resident
+ * launch record plus a published descriptor that the same persistent kernel
+ * consumes once the parent work is claimed.
+ *
+ * Conventions for every call below
+ *   - Graph arrays, outputs and the workspace are DEVICE pointers owned by the
+ *     caller; the library never allocates device memory and never frees the
+ *     caller's memory.  `stream` is a hipStream_t (NULL = default stream).
+ *   - The CSR graph must be symmetric for the results to be shortest paths of
+ *     an undirected graph; the kernels follow out-edges only.
+ *   - Work is enqueued on `stream`.  The traversal calls synchronise `stream`
+ *     once per `steps_per_replay` level steps to read the done flag, so they
+ *     return only when the traversal has finished and outputs are final.
+ *   - Errors are return codes, never exceptions.  Argument errors are found on
+ *     the host before anything is enqueued.  Device-detected errors (queue
+ *     capacity, a wait that exceeded its spin limit) are read back at the end
+ *     of the call.
+ *   - Not thread-safe for concurrent calls that share a workspace.
+ */
+#ifndef DPO_H
+#define DPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DPO_OK = 0,
+  DPO_ERR_ARG = -1,         /* null pointer, bad size or bad option             */
+  DPO_ERR_SOURCE = -2,      /* source outside [0, n)                             */
+  DPO_ERR_WORKSPACE = -3,   /* ws_bytes < dpo_workspace_bytes(...)               */
+  DPO_ERR_CAPACITY = -4,    /* a device queue would have overflowed              */
+  DPO_ERR_TIMEOUT = -5,     /* a device wait hit its spin limit, or level cap    */
+  DPO_ERR_HIP = -6,         /* a HIP runtime call failed                         */
+  DPO_ERR_UNSUPPORTED = -7  /* option combination not built into the library    */
+} dpo_status;
+
+typedef enum {
+  DPO_MODE_NESTED = 0, /* parent thread per frontier vertex + child work (T/C/A)   */
+  DPO_MODE_FLAT = 1    /* no nesting: each parent walks its neighbours serially
+                          (the paper's "No CDP" version, Sec. VII)              */
+} dpo_mode;
+
+typedef enum {
+  DPO_AGG_NONE = 0,       /* every launching parent publishes its own child grid
+                             (the paper's "CDP" version when T = 0, CF = 1)     */
+  DPO_AGG_WAVE = 1,       /* aggregation over the 64 parents of a wave
+                             (the paper's warp granularity, Sec. II-B)          */
+  DPO_AGG_BLOCK = 2,      /* over the 256 parents of a workgroup (Sec. II-B)    */
+  DPO_AGG_MULTIBLOCK = 3  /* over groups of agg_blocks workgroups (Sec. V-A)    */
+} dpo_agg;
+
+typedef struct {
+  int32_t mode;             /* dpo_mode                                             */
+  int32_t threshold;        /* T >= 0.  A parent of degree d, 0 < d < T, runs its
+                               children serially; d >= max(T, 1) launches
+                               (Sec. III-B).  T = 0 disables thresholding.         */
+  int32_t coarsen;          /* CF in {1, 2, 4, 8, 16}: one child block runs CF
+                               original child blocks (Sec. IV-B).                 */
+  int32_t agg;              /* dpo_agg (Sec. II-B, V-A)                             */
+  int32_t agg_blocks;       /* k >= 2 for DPO_AGG_MULTIBLOCK (e.g. 4 or 16)         */
+  int32_t child_block;      /* original child block size bDim in {64, 128, 256}    */
+  int32_t steps_per_replay; /* level steps per HIP-graph replay; 0 = 16            */
+} dpo_options;
+
+typedef struct {
+  int32_t n;                /* vertices, >= 1                                      */
+  int32_t m;                /* directed CSR entries, >= 0                          */
+  const int32_t* row_ptr;   /* device, int32[n + 1], row_ptr[0] = 0, row_ptr[n] = m */
+  const int32_t* col_idx;   /* device, int32[m], each in [0, n)                     */
+  const uint32_t* weights;  /* device, uint32[m] >= 1 (SSSP only; NULL for BFS)     */
+} dpo_csr;
+
+/* Per-traversal counters (host struct).  Requesting them makes the kernels
+ * count and adds one synchronising read at the end of the call. */
+typedef struct {
+  int32_t levels;           /* level steps with a non-empty frontier               */
+  int32_t reserved;
+  int64_t frontier_total;   /* parent threads run (sum of frontier sizes)          */
+  int64_t serial_parents;   /* parents that ran their children serially (T)        */
+  int64_t records;          /* parents that launched (launch records written)      */
+  int64_t child_blocks;     /* coarsened child blocks executed                     */
+  int64_t edges_serial;     /* neighbour visits done inside parents                */
+  int64_t edges_child;      /* neighbour visits done by child blocks               */
+  int64_t descriptors;      /* aggregated grids published ("launches")             */
+} dpo_stats;
+
+/* Fills *o with the defaults: nested, T = 128, CF = 8, 4-block aggregation,
+ * child block 256, 16 steps per replay. */
+void dpo_default_options(dpo_options* o);
+
+/* Device workspace bytes needed by dpo_bfs / dpo_sssp on a graph with g->n
+ * vertices under options o (the same buffer serves both).  0 on bad args.
+ * Layout, all inside the caller's buffer: traversal state and counters,
+ * two frontier queues of n int32, a per-vertex visit word (bitmap for BFS,
+ * iteration stamp for SSSP), n launch records of 16 bytes and the
+ * descriptor queue (16 bytes per possible aggregated grid). */
+size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o);
+
+/* Breadth-first search (Table I, BFS) from `source`.
+ * levels: device int32[g->n]; on return levels[v] = hop distance from the
+ * source, -1 if unreachable.  Bit-identical for every option combination.
+ * ws: device buffer of at least dpo_workspace_bytes(g, o) bytes, contents on
+ * entry irrelevant.  st: optional host pointer (NULL = no counters). */
+dpo_status dpo_bfs(const dpo_csr* g, int32_t source, const dpo_options* o, int32_t* levels,
+                   void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
+
+/* Single-source shortest paths (Table I, SSSP) by frontier Bellman-Ford with
+ * atomicMin relaxations.  g->weights required, each >= 1; n must be at most
+ * 16,843,009 so that every finite distance fits below 0xFFFFFFFF.
+ * dist: device uint32[g->n]; on return the exact shortest distances,
+ * 0xFFFFFFFF if unreachable.  Other arguments as for dpo_bfs. */
+dpo_status dpo_sssp(const dpo_csr* g, int32_t source, const dpo_options* o, uint32_t* dist,
+                    void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
+
+/* Static string for a dpo_status value. */
+const char* dpo_strerror(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPO_H */

@@ -1,0 +1,228 @@
+"""ctypes binding of libdpo.so (C ABI declared in include/dpo.h).
+
+Argument marshalling only: every step of a traversal runs in the HIP kernels
+of libdpo.so.  PyTorch provides device memory and the stream.  There is no
+CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpo.so")
+
+DPO_OK = 0
+DPO_ERR_ARG = -1
+DPO_ERR_SOURCE = -2
+DPO_ERR_WORKSPACE = -3
+DPO_ERR_CAPACITY = -4
+DPO_ERR_TIMEOUT = -5
+DPO_ERR_HIP = -6
+DPO_ERR_UNSUPPORTED = -7
+
+DPO_MODE_NESTED = 0
+DPO_MODE_FLAT = 1
+DPO_AGG_NONE = 0
+DPO_AGG_WAVE = 1
+DPO_AGG_BLOCK = 2
+DPO_AGG_MULTIBLOCK = 3
+
+UNREACHED_LEVEL = -1
+UNREACHED_DIST = 0xFFFFFFFF
+
+
+class DpoError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {dpo_strerror(status)} ({status})")
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("threshold", ctypes.c_int32),
+                ("coarsen", ctypes.c_int32), ("agg", ctypes.c_int32),
+                ("agg_blocks", ctypes.c_int32), ("child_block", ctypes.c_int32),
+                ("steps_per_replay", ctypes.c_int32)]
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("frontier_total", ctypes.c_int64), ("serial_parents", ctypes.c_int64),
+                ("records", ctypes.c_int64), ("child_blocks", ctypes.c_int64),
+                ("edges_serial", ctypes.c_int64), ("edges_child", ctypes.c_int64),
+                ("descriptors", ctypes.c_int64)]
+
+
+@dataclass
+class Options:
+    """Mirror of dpo_options.  Defaults = dpo_default_options()."""
+    mode: int = DPO_MODE_NESTED
+    threshold: int = 128
+    coarsen: int = 8
+    agg: int = DPO_AGG_MULTIBLOCK
+    agg_blocks: int = 4
+    child_block: int = 256
+    steps_per_replay: int = 0
+
+    def c(self) -> _Options:
+        return _Options(*(int(getattr(self, f.name)) for f in fields(self)))
+
+    @staticmethod
+    def flat(**kw) -> "Options":
+        return Options(mode=DPO_MODE_FLAT, **kw)
+
+    @staticmethod
+    def naive(**kw) -> "Options":
+        """One child grid per launching parent, no thresholding or coarsening
+        (the paper's plain dynamic-parallelism version)."""
+        kw.setdefault("threshold", 0)
+        kw.setdefault("coarsen", 1)
+        return Options(agg=DPO_AGG_NONE, **kw)
+
+    def label(self) -> str:
+        if self.mode == DPO_MODE_FLAT:
+            return "flat"
+        g = {0: "none", 1: "wave", 2: "block", 3: f"{self.agg_blocks}-block"}[self.agg]
+        return f"T{self.threshold}-CF{self.coarsen}-{g}"
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdpo.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.dpo_default_options.restype = None
+    L.dpo_default_options.argtypes = [ctypes.POINTER(_Options)]
+    L.dpo_workspace_bytes.restype = ctypes.c_size_t
+    L.dpo_workspace_bytes.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_Options)]
+    for name in ("dpo_bfs", "dpo_sssp"):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int32
+        f.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.POINTER(_Options),
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                      ctypes.POINTER(_Stats)]
+    L.dpo_strerror.restype = ctypes.c_char_p
+    L.dpo_strerror.argtypes = [ctypes.c_int32]
+    _lib = L
+    return L
+
+
+def dpo_strerror(status: int) -> str:
+    return lib().dpo_strerror(int(status)).decode()
+
+
+def dpo_default_options() -> Options:
+    o = _Options()
+    lib().dpo_default_options(ctypes.byref(o))
+    return Options(*(getattr(o, f) for f, _ in _Options._fields_))
+
+
+class DeviceGraph:
+    """Int32 CSR resident in device memory (torch tensors on ``device``)."""
+
+    def __init__(self, row_ptr, col_idx, weights=None):
+        self.row_ptr = row_ptr
+        self.col_idx = col_idx
+        self.weights = weights
+        self.n = int(row_ptr.numel() - 1)
+        self.m = int(col_idx.numel())
+
+    @classmethod
+    def from_host(cls, g, device="cuda"):
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int32)).to(device)
+        col = torch.from_numpy(np.ascontiguousarray(g.col_idx, dtype=np.int32)).to(device)
+        w = None
+        if g.weights is not None:
+            w = torch.from_numpy(np.ascontiguousarray(g.weights, dtype=np.uint32).view(np.int32))
+            w = w.to(device)
+        return cls(rp, col, w)
+
+    def csr(self) -> _Csr:
+        return _Csr(self.n, self.m, self.row_ptr.data_ptr(),
+                    self.col_idx.data_ptr() if self.m else None,
+                    self.weights.data_ptr() if self.weights is not None and self.m else None)
+
+
+def dpo_workspace_bytes(graph: DeviceGraph, opts: Options) -> int:
+    csr = _Csr(graph.n, graph.m, None, None, None)
+    return int(lib().dpo_workspace_bytes(ctypes.byref(csr), ctypes.byref(opts.c())))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _traverse(fn, what, graph, source, opts, out, ws, stream, stats):
+    st = _Stats() if stats else None
+    rc = fn(ctypes.byref(graph.csr()), int(source), ctypes.byref(opts.c()),
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(ws.numel() * ws.element_size()), _stream_ptr(stream),
+            ctypes.byref(st) if st is not None else None)
+    if rc != DPO_OK:
+        raise DpoError(rc, what)
+    if st is None:
+        return None
+    return {f: int(getattr(st, f)) for f, _ in _Stats._fields_ if f != "reserved"}
+
+
+def dpo_bfs(graph: DeviceGraph, source: int, opts: Options, levels, ws, stream=None,
+            stats: bool = False):
+    """levels: int32 device tensor [n] (written).  ws: device byte tensor of at
+    least dpo_workspace_bytes(graph, opts).  Returns counters if ``stats``."""
+    return _traverse(lib().dpo_bfs, "dpo_bfs", graph, source, opts, levels, ws, stream, stats)
+
+
+def dpo_sssp(graph: DeviceGraph, source: int, opts: Options, dist, ws, stream=None,
+             stats: bool = False):
+    """dist: int32/uint32 device tensor [n] (written as uint32)."""
+    return _traverse(lib().dpo_sssp, "dpo_sssp", graph, source, opts, dist, ws, stream, stats)
+
+
+def alloc_workspace(graph: DeviceGraph, opts: Options, device="cuda"):
+    import torch
+    return torch.empty(dpo_workspace_bytes(graph, opts), dtype=torch.uint8, device=device)
+
+
+def bfs(graph: DeviceGraph, source: int, opts: Options | None = None, stats: bool = False):
+    """Convenience: allocates the output and workspace, returns (levels, stats)."""
+    import torch
+    opts = opts or Options()
+    levels = torch.empty(graph.n, dtype=torch.int32, device=graph.row_ptr.device)
+    ws = alloc_workspace(graph, opts, graph.row_ptr.device)
+    st = dpo_bfs(graph, source, opts, levels, ws, stats=stats)
+    return levels, st
+
+
+def sssp(graph: DeviceGraph, source: int, opts: Options | None = None, stats: bool = False):
+    """Convenience: allocates the output and workspace, returns (dist, stats);
+    dist is an int32 tensor holding the uint32 bit patterns."""
+    import torch
+    opts = opts or Options()
+    dist = torch.empty(graph.n, dtype=torch.int32, device=graph.row_ptr.device)
+    ws = alloc_workspace(graph, opts, graph.row_ptr.device)
+    st = dpo_sssp(graph, source, opts, dist, ws, stats=stats)
+    return dist, st
+
+
+def as_uint32(t) -> np.ndarray:
+    """Host copy of a device int32 tensor reinterpreted as uint32."""
+    return t.cpu().numpy().view(np.uint32)

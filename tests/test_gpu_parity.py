@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+BFS levels and SSSP distances must be bit-identical to the oracle for every
+option combination (flat, naive, and the thresholding x coarsening x
+aggregation grid), and pass the edge certificates.  For BFS the per-traversal
+counters must also equal the oracle's schedule counts, which checks that the
+kernels threshold and coarsen as specified rather than only reaching the
+right answer.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_02789_amd import graphgen as gg
+from tests import certificates as cert
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2201_02789_amd import dpo  # noqa: E402
+
+SWEEP_T = [0, 8, 32, 128, 512]
+SWEEP_CF = [1, 2, 4, 8]
+SWEEP_G = [(dpo.DPO_AGG_WAVE, 0), (dpo.DPO_AGG_BLOCK, 0), (dpo.DPO_AGG_MULTIBLOCK, 4),
+           (dpo.DPO_AGG_MULTIBLOCK, 16)]
+
+
+def sweep_options():
+    out = [dpo.Options.flat(), dpo.Options.naive()]
+    for T, CF, (agg, k) in itertools.product(SWEEP_T, SWEEP_CF, SWEEP_G):
+        out.append(dpo.Options(threshold=T, coarsen=CF, agg=agg, agg_blocks=k or 4))
+    return out
+
+
+def run_bfs(dg, src, opts, ws=None, stats=True):
+    levels = torch.full((dg.n,), -7, dtype=torch.int32, device="cuda")
+    if ws is None:
+        ws = dpo.alloc_workspace(dg, opts)
+    st = dpo.dpo_bfs(dg, src, opts, levels, ws, stats=stats)
+    torch.cuda.synchronize()
+    return levels.cpu().numpy(), st
+
+
+def run_sssp(dg, src, opts, ws=None, stats=False):
+    dist = torch.full((dg.n,), 7, dtype=torch.int32, device="cuda")
+    if ws is None:
+        ws = dpo.alloc_workspace(dg, opts)
+    st = dpo.dpo_sssp(dg, src, opts, dist, ws, stats=stats)
+    torch.cuda.synchronize()
+    return dpo.as_uint32(dist), st
+
+
+def check_bfs_stats(g, lv, opts, st):
+    flat = opts.mode == dpo.DPO_MODE_FLAT
+    want = oracle.schedule_counts(g, lv, opts.threshold, opts.child_block, opts.coarsen, flat=flat)
+    got = {k: st[k] for k in want}
+    assert got == want, (opts.label(), got, want)
+    assert st["levels"] == int(lv.max()) + 1
+    if not flat:
+        assert 1 <= st["descriptors"] <= max(st["records"], 1) or st["records"] == 0
+
+
+@pytest.fixture(scope="module")
+def s12():
+    """Config 1: R-MAT scale 12, ef 16, unpermuted (vertex 0 is the hub)."""
+    g = gg.rmat(12, 16, 1)
+    return g, dpo.DeviceGraph.from_host(g)
+
+
+def test_config1_naive_bfs_s12(s12):
+    g, dg = s12
+    want, _ = oracle.bfs(g, 0)
+    got, st = run_bfs(dg, 0, dpo.Options.naive())
+    print("config1 naive", st, flush=True)
+    assert np.array_equal(got, want)
+    cert.check_bfs(g, 0, got)
+    check_bfs_stats(g, want, dpo.Options.naive(), st)
+
+
+def test_bfs_sweep_s12(s12):
+    g, dg = s12
+    want, _ = oracle.bfs(g, 0)
+    for opts in sweep_options():
+        print("bfs s12", opts.label(), flush=True)
+        got, st = run_bfs(dg, 0, opts)
+        assert np.array_equal(got, want), opts.label()
+        check_bfs_stats(g, want, opts, st)
+
+
+@pytest.mark.parametrize("cb", [64, 128])
+def test_bfs_small_child_blocks(s12, cb):
+    g, dg = s12
+    want, _ = oracle.bfs(g, 0)
+    for CF in (1, 4, 16):
+        opts = dpo.Options(threshold=16, coarsen=CF, child_block=cb)
+        got, st = run_bfs(dg, 0, opts)
+        assert np.array_equal(got, want), opts.label()
+        check_bfs_stats(g, want, opts, st)
+
+
+@pytest.fixture(scope="module")
+def s14p():
+    """Permuted R-MAT scale 14 with weights: frontiers of ragged size."""
+    g = gg.add_weights(gg.rmat(14, 16, 14, perm_seed=24), 31)
+    return g, dpo.DeviceGraph.from_host(g)
+
+
+def test_bfs_sweep_s14_permuted_several_sources(s14p):
+    g, dg = s14p
+    srcs = gg.sample_sources(g, 3, 1)
+    wants = [oracle.bfs(g, s)[0] for s in srcs]
+    for opts in sweep_options()[::3] + [dpo.Options()]:
+        ws = dpo.alloc_workspace(dg, opts)
+        for s, want in zip(srcs, wants):  # workspace reused across calls
+            print("bfs s14", opts.label(), int(s), flush=True)
+            got, st = run_bfs(dg, int(s), opts, ws=ws)
+            assert np.array_equal(got, want), (opts.label(), s)
+            check_bfs_stats(g, want, opts, st)
+
+
+def test_sssp_sweep_s14(s14p):
+    g, dg = s14p
+    src = gg.max_degree_vertex(g)
+    want = oracle.dijkstra(g, src)
+    for opts in sweep_options()[::2]:
+        print("sssp s14", opts.label(), flush=True)
+        got, st = run_sssp(dg, src, opts, stats=True)
+        assert np.array_equal(got, want), opts.label()
+        assert st["edges_serial"] + st["edges_child"] >= int(g.degrees()[want != 0xFFFFFFFF].sum())
+    cert.check_sssp(g, src, got)
+
+
+STRUCTURED = [
+    ("path", lambda: gg.path_graph(3000), 0),
+    ("cycle", lambda: gg.cycle_graph(1001), 7),
+    ("star", lambda: gg.star_graph(200_001), 0),
+    ("star-leaf", lambda: gg.star_graph(70_001), 5),
+    ("complete", lambda: gg.complete_graph(400), 3),
+    ("bintree", lambda: gg.binary_tree(100_000), 0),
+    ("grid", lambda: gg.grid_graph(300, 211), 0),
+    ("two-comp", lambda: gg.from_edges(10, [(1, 2), (2, 3), (5, 6)]), 2),
+    ("isolated", lambda: gg.from_edges(9, [(1, 2)]), 4),
+    ("single", lambda: gg.from_edges(1, []), 0),
+    ("road", lambda: gg.road_like(150, 170, 3), 11),
+]
+
+
+@pytest.mark.parametrize("name,make,src", STRUCTURED, ids=[s[0] for s in STRUCTURED])
+def test_structured_graphs(name, make, src):
+    g = gg.add_weights(make(), 9)
+    dg = dpo.DeviceGraph.from_host(g)
+    want, _ = oracle.bfs(g, src)
+    dwant = oracle.dijkstra(g, src)
+    for opts in (dpo.Options(), dpo.Options.flat(), dpo.Options.naive(),
+                 dpo.Options(threshold=0, coarsen=16, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=16),
+                 dpo.Options(threshold=4, coarsen=2, agg=dpo.DPO_AGG_WAVE, steps_per_replay=3)):
+        print(name, opts.label(), flush=True)
+        got, st = run_bfs(dg, src, opts)
+        assert np.array_equal(got, want), (name, opts.label())
+        check_bfs_stats(g, want, opts, st)
+        d, _ = run_sssp(dg, src, opts)
+        assert np.array_equal(d, dwant), (name, opts.label())
+
+
+def test_errors_reported():
+    g = gg.rmat(8, 8, 1)
+    dg = dpo.DeviceGraph.from_host(g)
+    opts = dpo.Options()
+    levels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ws = dpo.alloc_workspace(dg, opts)
+    with pytest.raises(dpo.DpoError) as e:
+        dpo.dpo_bfs(dg, g.n, opts, levels, ws)
+    assert e.value.status == dpo.DPO_ERR_SOURCE
+    with pytest.raises(dpo.DpoError) as e:
+        dpo.dpo_bfs(dg, 0, opts, levels, ws[:100])
+    assert e.value.status == dpo.DPO_ERR_WORKSPACE
+    with pytest.raises(dpo.DpoError) as e:
+        dpo.dpo_sssp(dg, 0, opts, levels, ws)  # no weights
+    assert e.value.status == dpo.DPO_ERR_ARG
+
+
+@pytest.fixture(scope="module")
+def s22():
+    """Config 2: R-MAT scale 22, ef 16, permuted, 16 sources."""
+    g = gg.rmat(22, 16, 22, perm_seed=24)
+    return g, dpo.DeviceGraph.from_host(g), gg.sample_sources(g, 16, 1)
+
+
+@pytest.mark.slow
+def test_bfs_s22_full_size(s22):
+    g, dg, srcs = s22
+    configs = [dpo.Options(), dpo.Options(threshold=32, coarsen=8, agg=dpo.DPO_AGG_BLOCK),
+               dpo.Options.flat(), dpo.Options.naive()]
+    wss = [dpo.alloc_workspace(dg, o) for o in configs]
+    for i, s in enumerate(srcs):
+        want, _ = oracle.bfs(g, int(s))
+        for o, ws in zip(configs, wss):
+            if o.mode == dpo.DPO_MODE_FLAT and i % 4:
+                continue  # the flat kernel is slow on hubs; every fourth source
+            print("bfs s22", o.label(), int(s), flush=True)
+            got, st = run_bfs(dg, int(s), o, ws=ws, stats=(i == 0))
+            assert np.array_equal(got, want), (o.label(), s)
+            if i == 0:
+                check_bfs_stats(g, want, o, st)
+                cert.check_bfs(g, int(s), got)
+
+
+@pytest.mark.slow
+def test_sssp_s21_full_size():
+    g = gg.add_weights(gg.rmat(21, 16, 21, perm_seed=24), 31)
+    dg = dpo.DeviceGraph.from_host(g)
+    src = gg.max_degree_vertex(g)
+    want = oracle.dijkstra(g, src)
+    for o in (dpo.Options(), dpo.Options.flat(), dpo.Options(threshold=32, coarsen=4,
+                                                               agg=dpo.DPO_AGG_BLOCK)):
+        print("sssp s21", o.label(), flush=True)
+        got, _ = run_sssp(dg, src, o)
+        assert np.array_equal(got, want), o.label()
+    cert.check_sssp(g, src, got)
