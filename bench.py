@@ -1,0 +1,283 @@
+#!/usr/bin/env python3
+"""Benchmark: GTEPS of nested-parallel BFS on R-MAT scale 22 (edgefactor 16,
+16 sources) with thresholding + coarsening + aggregation, beside the flat
+(no nesting) and naive (one child grid per parent) kernels on the same GPU,
+the HBM roofline of the level-step kernel, and the CPU oracle on host cores.
+
+A step is one pass of the whole hot path over the batch: one BFS from each of
+the 16 sources.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload bfs22|sssp21]
+                  [--sweep] [--no-cpu] [--no-baselines]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="bfs22", choices=["bfs22", "sssp21", "bfs12"])
+    p.add_argument("--threshold", type=int, default=None)
+    p.add_argument("--coarsen", type=int, default=None)
+    p.add_argument("--agg", default=None, help="none|wave|block|<k>-block")
+    p.add_argument("--sweep", action="store_true", help="config-2 sweep table instead")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-baselines", action="store_true")
+    p.add_argument("--cpu-sources", type=int, default=4)
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def agg_of(s):
+    from paper_2201_02789_amd import dpo
+    if s is None:
+        return None
+    if s == "none":
+        return (dpo.DPO_AGG_NONE, 4)
+    if s == "wave":
+        return (dpo.DPO_AGG_WAVE, 4)
+    if s == "block":
+        return (dpo.DPO_AGG_BLOCK, 4)
+    return (dpo.DPO_AGG_MULTIBLOCK, int(s.split("-")[0]))
+
+
+# Best point of the config-2 sweep on MI355X; overridable.
+TUNED = {"bfs22": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
+         "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
+         "sssp21": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4)}
+
+
+class Workload:
+    def __init__(self, name):
+        from paper_2201_02789_amd import graphgen as gg
+        self.name = name
+        t0 = time.time()
+        if name == "bfs22":
+            self.g = gg.rmat(22, 16, 22, perm_seed=24)
+            self.sources = gg.sample_sources(self.g, 16, 1)
+            self.kind = "bfs"
+            self.desc = "BFS, R-MAT scale 22, edgefactor 16, a/b/c/d .57/.19/.19/.05, permuted, 16 sources"
+        elif name == "bfs12":
+            self.g = gg.rmat(12, 16, 1)
+            self.sources = np.array([0], dtype=np.int32)
+            self.kind = "bfs"
+            self.desc = "BFS, R-MAT scale 12, edgefactor 16, unpermuted, source 0"
+        else:
+            self.g = gg.add_weights(gg.rmat(21, 16, 21, perm_seed=24), 31)
+            self.sources = np.array([gg.max_degree_vertex(self.g)], dtype=np.int32)
+            self.kind = "sssp"
+            self.desc = "SSSP, R-MAT scale 21, edgefactor 16, weights U[1,255], max-degree source"
+        log(f"[bench] graph {name}: n={self.g.n} m={self.g.m} ({time.time() - t0:.1f}s)")
+
+
+def run_one(dpo, dg, kind, src, opts, out, ws):
+    if kind == "bfs":
+        return dpo.dpo_bfs(dg, int(src), opts, out, ws)
+    return dpo.dpo_sssp(dg, int(src), opts, out, ws)
+
+
+def measure(dpo, torch, wl, dg, opts, steps, warmup, sources=None):
+    """Times `steps` passes over the sources; returns per-call event times (ms)."""
+    sources = wl.sources if sources is None else sources
+    out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
+    ws = dpo.alloc_workspace(dg, opts)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        for s in sources:
+            run_one(dpo, dg, wl.kind, s, opts, out, ws)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps * len(sources))]
+    t0 = time.perf_counter()
+    i = 0
+    for _ in range(steps):
+        for s in sources:
+            ev[i][0].record(stream)
+            run_one(dpo, dg, wl.kind, s, opts, out, ws)
+            ev[i][1].record(stream)
+            i += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_call = np.array([a.elapsed_time(b) for a, b in ev]).reshape(steps, len(sources))
+    return per_call, wall
+
+
+def reached_stats(dpo, torch, wl, dg, opts):
+    """(m_r, n_r, levels) per source, from one untimed run with counters."""
+    out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
+    ws = dpo.alloc_workspace(dg, opts)
+    deg = np.diff(wl.g.row_ptr).astype(np.int64)
+    res = []
+    for s in wl.sources:
+        if wl.kind == "bfs":
+            st = dpo.dpo_bfs(dg, int(s), opts, out, ws, stats=True)
+            reached = out.cpu().numpy() >= 0
+        else:
+            st = dpo.dpo_sssp(dg, int(s), opts, out, ws, stats=True)
+            reached = dpo.as_uint32(out) != 0xFFFFFFFF
+        res.append((int(deg[reached].sum()), int(reached.sum()), st))
+    return res
+
+
+def algorithmic_bytes(kind, m_r, n_r):
+    # BFS: col_idx + level probe per edge, row_ptr pair + level write + frontier
+    # write/read per reached vertex.  SSSP: col + weight + dist probe per edge.
+    return (8 * m_r + 20 * n_r) if kind == "bfs" else (12 * m_r + 24 * n_r)
+
+
+def cpu_baseline(wl, nsrc):
+    import oracle
+    srcs = wl.sources[:nsrc]
+    t0 = time.perf_counter()
+    edges = 0
+    for s in srcs:
+        if wl.kind == "bfs":
+            lv, _ = oracle.bfs(wl.g, int(s))
+            reached = lv >= 0
+        else:
+            d = oracle.dijkstra(wl.g, int(s))
+            reached = d != 0xFFFFFFFF
+        edges += int(np.diff(wl.g.row_ptr)[reached].sum())
+    dt = time.perf_counter() - t0
+    return {"value": round(edges / 2 / dt / 1e9, 4), "unit": "GTEPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{len(srcs)} of the {len(wl.sources)} sources, one full "
+                      f"{'queue BFS' if wl.kind == 'bfs' else 'binary-heap Dijkstra'} each, "
+                      f"single thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "independent traversals shard by graph across GPUs, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2201_02789_amd import dpo
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dpo.lib()  # fail loudly if the HIP library is missing
+
+    wl = Workload(args.workload)
+    dg = dpo.DeviceGraph.from_host(wl.g)
+    tuned = dict(TUNED[args.workload])
+    if args.threshold is not None:
+        tuned["threshold"] = args.threshold
+    if args.coarsen is not None:
+        tuned["coarsen"] = args.coarsen
+    a = agg_of(args.agg)
+    if a:
+        tuned["agg"], tuned["agg_blocks"] = a
+    opts = dpo.Options(**tuned)
+
+    if args.sweep:
+        return sweep(dpo, torch, wl, dg)
+
+    # untimed run with counters: edges reached and level count per source
+    rs = reached_stats(dpo, torch, wl, dg, opts)
+    levels = max(r[2]["levels"] for r in rs)
+    opts.steps_per_replay = levels + 1  # one replay covers a traversal
+    m_r = np.array([r[0] for r in rs], dtype=np.float64)
+    n_r = np.array([r[1] for r in rs], dtype=np.float64)
+    log(f"[bench] options {opts.label()} steps/replay {opts.steps_per_replay}; "
+        f"m_r mean {m_r.mean():.0f}, n_r mean {n_r.mean():.0f}")
+
+    per_call, wall = measure(dpo, torch, wl, dg, opts, args.steps, args.warmup)
+    t_step_ms = per_call.sum(axis=1)  # ms per step (all sources)
+    total_ms = float(per_call.sum())
+    edges_step = float((m_r / 2).sum())
+    gteps = args.steps * edges_step / (total_ms * 1e-3) / 1e9
+    log(f"[bench] T+C+A: {gteps:.2f} GTEPS, {t_step_ms.mean():.3f} ms/step, wall {wall:.3f}s")
+
+    # roofline of the level-step kernel: algorithmic bytes per launch / mean
+    # launch duration, both per traversal divided by its launch count
+    launches = np.array([r[2]["levels"] + 1 for r in rs], dtype=np.float64)
+    bytes_call = algorithmic_bytes(wl.kind, m_r, n_r)
+    mean_call_ms = per_call.mean(axis=0)
+    achieved = float((bytes_call.sum() / launches.sum()) /
+                     ((mean_call_ms.sum() * 1e-3) / launches.sum()) / 1e9)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"step_kernel<{wl.kind.upper()},{opts.label()}>",
+                "launches_per_traversal": float(launches.mean()),
+                "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
+                "algorithmic_bytes_per_launch": round(float(bytes_call.sum() / launches.sum()))}
+
+    baselines = {}
+    if not args.no_baselines:
+        for name, o in (("flat", dpo.Options.flat()), ("naive", dpo.Options.naive())):
+            o.steps_per_replay = opts.steps_per_replay
+            pc, _ = measure(dpo, torch, wl, dg, o, 1, 1)
+            g_b = edges_step / (pc.sum() * 1e-3) / 1e9
+            baselines[name] = {"gteps": round(g_b, 3), "ms_per_step": round(float(pc.sum()), 3),
+                               "options": o.label()}
+            log(f"[bench] {name}: {g_b:.3f} GTEPS")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, min(args.cpu_sources, len(wl.sources)))
+        log(f"[bench] oracle: {cpu['value']} GTEPS ({cpu['sample']})")
+
+    line = {
+        "metric": "GTEPS (BFS/SSSP, R-MAT s22) vs flat & naive-nested",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(float(t_step_ms.mean()), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded R-MAT, stands in for the paper's Kronecker graph)",
+        "config": {"workload": wl.desc, "n": wl.g.n, "m": wl.g.m,
+                   "sources": int(len(wl.sources)), "options": opts.label(),
+                   "steps_per_replay": opts.steps_per_replay,
+                   "mean_reached_edges": float(m_r.mean()),
+                   "gteps_convention": "undirected edges in the reached component / time, "
+                                       "summed over sources"},
+        "roofline": roofline,
+        "baselines": baselines,
+        "speedup_vs_flat": round(gteps / baselines["flat"]["gteps"], 2) if baselines else None,
+        "speedup_vs_naive": round(gteps / baselines["naive"]["gteps"], 2) if baselines else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def sweep(dpo, torch, wl, dg):
+    """Config-2 sweep: T x CF x granularity, plus flat and naive (JSON lines)."""
+    import itertools
+    rs = reached_stats(dpo, torch, wl, dg, dpo.Options())
+    edges = float(sum(r[0] for r in rs) / 2)
+    steps = max(r[2]["levels"] for r in rs) + 1
+    grid = [dpo.Options.flat(), dpo.Options.naive()]
+    for T, CF, (agg, k) in itertools.product([0, 8, 32, 128, 512], [1, 2, 4, 8],
+                                             [(1, 4), (2, 4), (3, 4), (3, 16)]):
+        grid.append(dpo.Options(threshold=T, coarsen=CF, agg=agg, agg_blocks=k))
+    for o in grid:
+        o.steps_per_replay = steps
+        pc, _ = measure(dpo, torch, wl, dg, o, 2, 1)
+        g = 2 * edges / (pc.sum() * 1e-3) / 1e9
+        print(json.dumps({"options": o.label(), "gteps": round(g, 3),
+                          "ms_per_traversal": round(float(pc.mean()), 4)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

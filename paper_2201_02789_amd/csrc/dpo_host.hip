@@ -21,14 +21,12 @@ namespace {
 
 constexpr int kDefaultSteps = 16;
 constexpr int kMaxCachedGraphs = 64;
-constexpr uint64_t kTicksPerMs = 100000;  // s_memrealtime runs at 100 MHz
-constexpr uint64_t kDefaultWatchdogMs = 4000;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t state, grp_packed, grp_done, front0, front1, visit, rec, desc_a, desc_b, total;
-  int32_t ngroups_cap, desc_cap;
+  size_t state, grp_packed, grp_done, front0, front1, visit, rec, desc, stats, total;
+  int32_t ngroups_cap, desc_cap, fcap;
 };
 
 int gran_of(const dpo_options& o) {
@@ -42,29 +40,35 @@ int gran_of(const dpo_options& o) {
   }
 }
 
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 Layout layout_for(int32_t n, const dpo_options& o) {
   Layout L{};
   const int gran = gran_of(o);
-  const int64_t nvb = (n + PB - 1) / PB;
+  const int64_t nvb = cdiv(n, PB);
   const int64_t k = (gran == AGG_MULTI) ? o.agg_blocks : 1;
-  L.ngroups_cap = (gran == AGG_MULTI) ? (int32_t)((nvb + k - 1) / k) : 1;
+  L.ngroups_cap = (gran == AGG_MULTI) ? (int32_t)cdiv(nvb, k) : 1;
+  // descriptors per queue: virtual block vb publishes to queue vb % NQD
+  // (multi-block group g to queue g % NQD)
   switch (gran) {
-    case AGG_NONE: L.desc_cap = n; break;
-    case AGG_WAVE: L.desc_cap = (n + 63) / 64; break;
-    case AGG_BLOCK: L.desc_cap = (int32_t)nvb; break;
-    case AGG_MULTI: L.desc_cap = L.ngroups_cap; break;
+    case AGG_NONE: L.desc_cap = (int32_t)(PB * cdiv(nvb, NQD)); break;
+    case AGG_WAVE: L.desc_cap = (int32_t)(NW * cdiv(nvb, NQD)); break;
+    case AGG_BLOCK: L.desc_cap = (int32_t)cdiv(nvb, NQD); break;
+    case AGG_MULTI: L.desc_cap = (int32_t)cdiv(L.ngroups_cap, NQD); break;
     default: L.desc_cap = 1; break;
   }
+  L.fcap = (int32_t)(2 * cdiv(n, NQF) + 64);
+  const size_t fslots = (size_t)NQF * L.fcap + (size_t)n;
   size_t off = 0;
   L.state = off; off = align_up(off + sizeof(State));
   L.grp_packed = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 8);
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
-  L.front0 = off; off = align_up(off + (size_t)n * 4);
-  L.front1 = off; off = align_up(off + (size_t)n * 4);
+  L.front0 = off; off = align_up(off + fslots * 4);
+  L.front1 = off; off = align_up(off + fslots * 4);
   L.visit = off; off = align_up(off + (size_t)n * 4);
   L.rec = off; off = align_up(off + (size_t)n * 16);
-  L.desc_a = off; off = align_up(off + (size_t)L.desc_cap * 8);
-  L.desc_b = off; off = align_up(off + (size_t)L.desc_cap * 8);
+  L.desc = off; off = align_up(off + (size_t)NQD * L.desc_cap * 16);
+  L.stats = off; off = align_up(off + (size_t)MAX_GRID * NSTAT * 8);
   L.total = off;
   return L;
 }
@@ -89,9 +93,9 @@ dpo_status check_graph(const dpo_csr* g, bool need_w) {
 }
 
 struct CachedGraph {
-  const void* kernel;
-  int grid;
-  int steps;
+  const void* parent;
+  const void* child;
+  int pgrid, cgrid, steps;
   Args args;
   hipGraphExec_t exec;
   uint64_t last_use;
@@ -101,10 +105,9 @@ struct Runtime {
   std::mutex mu;
   std::vector<CachedGraph> graphs;
   uint64_t tick = 0;
-  uint32_t* host_flags = nullptr;  // pinned: level, done, error, levels_run
-  unsigned long long* host_stats = nullptr;
+  uint32_t* host_flags = nullptr;  // pinned: base, done, error, levels_run
+  unsigned long long* host_stats = nullptr;  // pinned: MAX_GRID * NSTAT
   int cu_count = 0;
-  uint64_t watchdog_ticks = 0;
   std::vector<std::pair<const void*, int>> grids;
 };
 
@@ -122,15 +125,10 @@ dpo_status ensure_runtime(Runtime& r) {
   if (hipDeviceGetAttribute(&r.cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return DPO_ERR_HIP;
   void* p = nullptr;
-  if (hipHostMalloc(&p, 256, hipHostMallocDefault) != hipSuccess) return DPO_ERR_HIP;
+  if (hipHostMalloc(&p, 256 + (size_t)MAX_GRID * NSTAT * 8, hipHostMallocDefault) != hipSuccess)
+    return DPO_ERR_HIP;
   r.host_flags = (uint32_t*)p;
-  r.host_stats = (unsigned long long*)((char*)p + 64);
-  uint64_t ms = kDefaultWatchdogMs;
-  if (const char* env = std::getenv("DPO_WATCHDOG_MS")) {
-    long v = std::atol(env);
-    if (v > 0) ms = (uint64_t)v;
-  }
-  r.watchdog_ticks = ms * kTicksPerMs;
+  r.host_stats = (unsigned long long*)((char*)p + 256);
   return DPO_OK;
 }
 
@@ -144,15 +142,35 @@ int persistent_grid(Runtime& r, const void* kernel) {
     per_cu = 1;
   if (per_cu > 8) per_cu = 8;
   int grid = per_cu * r.cu_count;
+  if (grid > MAX_GRID) grid = MAX_GRID;
   r.grids.emplace_back(kernel, grid);
   return grid;
 }
 
-dpo_status get_exec(Runtime& r, const void* kernel, int grid, int steps, const Args& args,
-                    hipGraphExec_t* out) {
+dpo_status add_node(hipGraph_t graph, hipGraphNode_t* prev, const void* fn, int grid, int block,
+                    void** params) {
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(fn);
+  kp.gridDim = dim3(grid);
+  kp.blockDim = dim3(block);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = params;
+  kp.extra = nullptr;
+  hipGraphNode_t node;
+  if (hipGraphAddKernelNode(&node, graph, *prev ? prev : nullptr, *prev ? 1 : 0, &kp) !=
+      hipSuccess)
+    return DPO_ERR_HIP;
+  *prev = node;
+  return DPO_OK;
+}
+
+// K level steps (parent kernel, then child kernel unless flat) and the
+// advance of the level base, as one instantiated graph.
+dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid, int cgrid,
+                    int steps, const Args& args, hipGraphExec_t* out) {
   for (auto& e : r.graphs) {
-    if (e.kernel == kernel && e.grid == grid && e.steps == steps &&
-        std::memcmp(&e.args, &args, sizeof(Args)) == 0) {
+    if (e.parent == parent && e.child == child && e.pgrid == pgrid && e.cgrid == cgrid &&
+        e.steps == steps && std::memcmp(&e.args, &args, sizeof(Args)) == 0) {
       e.last_use = ++r.tick;
       *out = e.exec;
       return DPO_OK;
@@ -161,28 +179,24 @@ dpo_status get_exec(Runtime& r, const void* kernel, int grid, int steps, const A
   hipGraph_t graph;
   if (hipGraphCreate(&graph, 0) != hipSuccess) return DPO_ERR_HIP;
   Args a = args;
-  void* params[] = {&a};
-  hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(kernel);
-  kp.gridDim = dim3(grid);
-  kp.blockDim = dim3(PB);
-  kp.sharedMemBytes = 0;
-  kp.kernelParams = params;
-  kp.extra = nullptr;
+  std::vector<uint32_t> step_ids(steps);
   hipGraphNode_t prev = nullptr;
-  for (int i = 0; i < steps; ++i) {
-    hipGraphNode_t node;
-    if (hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp) !=
-        hipSuccess) {
-      hipGraphDestroy(graph);
-      return DPO_ERR_HIP;
-    }
-    prev = node;
+  dpo_status s = DPO_OK;
+  for (int i = 0; i < steps && s == DPO_OK; ++i) {
+    step_ids[i] = (uint32_t)i;
+    void* params[] = {&a, &step_ids[i]};
+    s = add_node(graph, &prev, parent, pgrid, PB, params);
+    if (s == DPO_OK && child) s = add_node(graph, &prev, child, cgrid, PB, params);
   }
+  State* st = a.st;
+  uint32_t k = (uint32_t)steps;
+  void* aparams[] = {&st, &k};
+  if (s == DPO_OK) s = add_node(graph, &prev, advance_kernel_ptr(), 1, 64, aparams);
   hipGraphExec_t exec;
-  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (s == DPO_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+    s = DPO_ERR_HIP;
   hipGraphDestroy(graph);
-  if (e != hipSuccess) return DPO_ERR_HIP;
+  if (s != DPO_OK) return s;
   if ((int)r.graphs.size() >= kMaxCachedGraphs) {
     size_t victim = 0;
     for (size_t i = 1; i < r.graphs.size(); ++i)
@@ -190,7 +204,7 @@ dpo_status get_exec(Runtime& r, const void* kernel, int grid, int steps, const A
     hipGraphExecDestroy(r.graphs[victim].exec);
     r.graphs.erase(r.graphs.begin() + victim);
   }
-  r.graphs.push_back(CachedGraph{kernel, grid, steps, args, exec, ++r.tick});
+  r.graphs.push_back(CachedGraph{parent, child, pgrid, cgrid, steps, args, exec, ++r.tick});
   *out = exec;
   return DPO_OK;
 }
@@ -207,8 +221,9 @@ dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_opt
   const Layout lay = layout_for(g->n, *o);
   if (ws_bytes < lay.total) return DPO_ERR_WORKSPACE;
   const int gran = gran_of(*o);
-  const void* kernel = step_kernel_ptr(problem, gran, gran == AGG_FLAT ? 1 : o->coarsen);
-  if (!kernel) return DPO_ERR_UNSUPPORTED;
+  const void* parent = parent_kernel_ptr(problem, gran);
+  const void* child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem, o->coarsen);
+  if (!parent || (gran != AGG_FLAT && !child)) return DPO_ERR_UNSUPPORTED;
   hipStream_t stream = (hipStream_t)stream_;
 
   Runtime& r = rt();
@@ -231,26 +246,28 @@ dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_opt
   a.front1 = (int32_t*)(base + lay.front1);
   a.visit = (uint32_t*)(base + lay.visit);
   a.rec = (int4*)(base + lay.rec);
-  a.desc_a = (unsigned long long*)(base + lay.desc_a);
-  a.desc_b = (unsigned long long*)(base + lay.desc_b);
+  a.desc = (int4*)(base + lay.desc);
+  a.stats = (unsigned long long*)(base + lay.stats);
   a.n = g->n;
   a.m = g->m;
   a.T = o->threshold;
   a.CB = o->child_block;
+  a.CF = o->coarsen;
   a.k = (gran == AGG_MULTI) ? o->agg_blocks : 1;
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
+  a.fcap = lay.fcap;
   a.count_stats = st ? 1 : 0;
-  a.watchdog_ticks = r.watchdog_ticks;
 
-  const int grid = persistent_grid(r, kernel);
+  const int pgrid = persistent_grid(r, parent);
+  const int cgrid = child ? persistent_grid(r, child) : 0;
   const int steps = o->steps_per_replay ? o->steps_per_replay : kDefaultSteps;
   hipGraphExec_t exec;
-  s = get_exec(r, kernel, grid, steps, a, &exec);
+  s = get_exec(r, parent, child, pgrid, cgrid, steps, a, &exec);
   if (s != DPO_OK) return s;
 
-  // init: enough workgroups to sweep n (and the descriptor flags) quickly
-  int init_grid = (int)((std::max<int64_t>(g->n, lay.desc_cap) + PB - 1) / PB);
+  // init: enough workgroups to sweep n quickly
+  int init_grid = (int)((std::max<int64_t>(g->n, MAX_GRID * NSTAT) + PB - 1) / PB);
   if (init_grid > 4 * r.cu_count) init_grid = 4 * r.cu_count;
   if (init_grid < 1) init_grid = 1;
   void* iparams[] = {&a, &source};
@@ -275,19 +292,22 @@ dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_opt
   }
   if (!finished) return DPO_ERR_TIMEOUT;
   if (st) {
-    if (hipMemcpyAsync(r.host_stats, a.st->stats, 8 * sizeof(unsigned long long),
-                       hipMemcpyDeviceToHost, stream) != hipSuccess ||
+    if (hipMemcpyAsync(r.host_stats, a.stats, (size_t)MAX_GRID * NSTAT * 8, hipMemcpyDeviceToHost,
+                       stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return DPO_ERR_HIP;
+    int64_t sum[NSTAT] = {0};
+    for (int w = 0; w < MAX_GRID; ++w)
+      for (int k = 0; k < NSTAT; ++k) sum[k] += (int64_t)r.host_stats[w * NSTAT + k];
     std::memset(st, 0, sizeof(*st));
     st->levels = (int32_t)r.host_flags[3];
-    st->frontier_total = (int64_t)r.host_stats[0];
-    st->serial_parents = (int64_t)r.host_stats[1];
-    st->records = (int64_t)r.host_stats[2];
-    st->child_blocks = (int64_t)r.host_stats[3];
-    st->edges_serial = (int64_t)r.host_stats[4];
-    st->edges_child = (int64_t)r.host_stats[5];
-    st->descriptors = (int64_t)r.host_stats[6];
+    st->frontier_total = sum[S_FRONT];
+    st->serial_parents = sum[S_SERIAL];
+    st->records = sum[S_REC];
+    st->child_blocks = sum[S_CHILD];
+    st->edges_serial = sum[S_ESER];
+    st->edges_child = sum[S_ECHILD];
+    st->descriptors = sum[S_DESC];
   }
   return DPO_OK;
 }

@@ -1,9 +1,10 @@
 // Device code: level-synchronous nested-parallel BFS / SSSP for gfx950.
 //
-// One level step is one persistent kernel.  Workgroups (256 lanes = 4 wave64)
-// first claim virtual parent blocks of 256 frontier entries (the parent
-// grid), then turn into consumers of the child grids those parents
-// "launched".  Per parent thread u with child-thread count deg(u)
+// Each level is two kernels.
+//
+// Parent kernel: the parent grid.  Workgroups (256 lanes = 4 wave64) take
+// virtual parent blocks of 256 frontier entries in a grid-stride loop; lane i
+// is the parent thread of frontier vertex u with child-thread count deg(u)
 // (Sec. III-D):
 //
 //   deg == 0            nothing to do
@@ -20,31 +21,34 @@
 // grid), wave (64 parents), block (256 parents) and multi-block (k blocks).
 // Multi-block groups take their record slot and offset from one packed 64-bit
 // atomic per group (hi = records, lo = child blocks; Sec. V-A increments both
-// counters as one integer), pre-aggregated per block, and the last block of
-// the group (group-wide done counter) publishes the aggregated grid.
+// counters as one integer), pre-aggregated per block; a group-wide done
+// counter picks the last block, which publishes the aggregated grid.
 //
 // HIP has no device-side launch.  "Publishing" appends a descriptor {record
-// segment, record count, global child-block base} to a queue through a second
-// packed 64-bit counter (hi = descriptors, lo = child blocks), so descriptor
-// bases grow with the descriptor index.  Consumers take global child-block
-// tickets, find the descriptor by a wave-parallel 64-ary search over the
-// bases, then their parent record by the same search over the scanned
-// offsets (the disaggregation of Sec. V-A), and run the coarsening loop over
-// CF original blocks of CB lanes (Sec. IV-B) with coalesced col_idx reads.
+// base, record count, child-block base} to one of eight queues through a
+// packed 64-bit counter (hi = descriptors, lo = child blocks), so block bases
+// grow with the descriptor index.  The launch itself is the stream-ordered
+// child kernel that follows: the kernel boundary makes records visible
+// without the release/acquire fences an in-kernel hand-off would need.
 //
-// Child body: BFS claims v in a visited bitmap (an L2-resident n-bit array)
-// and writes level[v] = L + 1; SSSP relaxes dist[v] with atomicMin and
-// queues v once per iteration through an iteration stamp.  Discovered vertices
-// are staged per wave in LDS and appended to the next frontier with one atomic
-// per flush.
+// Child kernel: the aggregated child grids.  Workgroup w runs a contiguous
+// share of the child blocks, finds the parent of its first block by 64-ary
+// wave searches of the descriptor bases and the scanned record offsets (the
+// disaggregation of Sec. V-A), then advances along the scanned offsets.  Each
+// coarsened block runs the coarsening loop over CF original blocks of CB lanes
+// (Sec. IV-B) with coalesced col_idx reads.
+//
+// Child body: BFS claims v in a visited bitmap (n bits, L2-resident) and
+// writes level[v] = L + 1; SSSP relaxes dist[v] with atomicMin and queues v
+// once per iteration through an iteration stamp.  New frontier vertices are
+// staged per wave in LDS and appended to one of 64 frontier queues with one
+// atomic per flush, so no counter sees more than a few dozen atomics a level.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "dpo_internal.h"
 
 namespace dpo {
-
-#define AGENT __HIP_MEMORY_SCOPE_AGENT
 
 __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -70,42 +74,99 @@ __device__ __forceinline__ void set_error(State* st, uint32_t code) {
   atomicCAS(&st->error, 0u, code);
 }
 
-__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+__device__ __forceinline__ uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
-// Per-wave LDS staging of next-frontier vertices.
+// ------------------------------------------------------------ frontier queues
+// Next frontier = NQF queues of fcap slots plus an overflow queue of n slots.
+struct Reserve {
+  uint32_t q, pos, inseg, obase;
+};
+
+// Reserve `cnt` slots in queue q (one lane).  Slots past fcap spill into the
+// overflow queue.
+__device__ __forceinline__ Reserve reserve_slots(const Args& a, LevelSet* ls, uint32_t q,
+                                                 uint32_t cnt) {
+  Reserve r{q, 0u, 0u, 0u};
+  const uint32_t old = atomicAdd(&ls->fcnt[q], cnt);
+  r.pos = old;
+  r.inseg = old >= (uint32_t)a.fcap ? 0u : min(cnt, (uint32_t)a.fcap - old);
+  if (r.inseg < cnt) {
+    const uint32_t rest = cnt - r.inseg;
+    r.obase = atomicAdd(&ls->fcnt[NQF], rest);
+    if ((uint64_t)r.obase + rest > (uint64_t)a.n) set_error(a.st, ERR_CAPACITY);
+  }
+  return r;
+}
+
+__device__ __forceinline__ void put_slot(const Args& a, int32_t* buf, const Reserve& r, uint32_t p,
+                                         int32_t v) {
+  if (p < r.inseg) {
+    buf[(size_t)r.q * a.fcap + r.pos + p] = v;
+  } else {
+    const uint32_t o = r.obase + (p - r.inseg);
+    if (o < (uint32_t)a.n) buf[(size_t)NQF * a.fcap + o] = v;
+  }
+}
+
 struct Stage {
-  int32_t* buf;  // STAGE slots in LDS owned by this wave
+  int32_t* buf;  // STAGE LDS slots owned by this wave
   uint32_t cnt;  // wave-uniform fill
 };
 
-__device__ __noinline__ void stage_flush(Stage& s, const Args& a, int32_t* fout,
-                                         uint32_t* fcount, int lane) {
+// Flush one wave's staged vertices (wave-uniform call).
+__device__ __noinline__ void stage_flush(Stage& s, const Args& a, LevelSet* ls, int32_t* fout,
+                                         int lane) {
   if (s.cnt == 0) return;
-  uint32_t base = 0;
-  if (lane == 0) base = atomicAdd(fcount, s.cnt);
-  base = __shfl(base, 0, 64);
+  Reserve r{0u, 0u, 0u, 0u};
+  if (lane == 0) r = reserve_slots(a, ls, blockIdx.x % NQF, s.cnt);
+  r.q = __shfl(r.q, 0, 64);
+  r.pos = __shfl(r.pos, 0, 64);
+  r.inseg = __shfl(r.inseg, 0, 64);
+  r.obase = __shfl(r.obase, 0, 64);
   wave_lds_sync();
-  if ((uint64_t)base + s.cnt > (uint64_t)a.n) {
-    if (lane == 0) set_error(a.st, ERR_CAPACITY);
-  } else {
-    for (uint32_t i = lane; i < s.cnt; i += 64) fout[base + i] = s.buf[i];
-  }
+  for (uint32_t i = lane; i < s.cnt; i += 64) put_slot(a, fout, r, i, s.buf[i]);
   wave_lds_sync();
   s.cnt = 0;
 }
 
 // Wave-uniform call: every lane of the wave must reach it.
 __device__ __forceinline__ void stage_push(Stage& s, bool found, int32_t v, const Args& a,
-                                           int32_t* fout, uint32_t* fcount, int lane) {
-  unsigned long long m = __ballot(found);
+                                           LevelSet* ls, int32_t* fout, int lane) {
+  const unsigned long long m = __ballot(found);
   if (m == 0) return;
-  uint32_t c = (uint32_t)__popcll(m);
-  if (s.cnt + c > STAGE) stage_flush(s, a, fout, fcount, lane);
+  const uint32_t c = (uint32_t)__popcll(m);
+  if (s.cnt + c > STAGE) stage_flush(s, a, ls, fout, lane);
   if (found) s.buf[s.cnt + lane_rank(m)] = v;
   s.cnt += c;
 }
 
-// Child body for one neighbour (one original child thread).
+// End of kernel: one reservation for the whole workgroup.  Block-uniform call.
+__device__ void block_flush(Stage& s, const Args& a, LevelSet* ls, int32_t* fout, int tid,
+                            uint32_t* s_cnt /* LDS [NW + 5] */) {
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0) s_cnt[wave] = s.cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < NW; ++w) tot += s_cnt[w];
+    Reserve r{0u, 0u, 0u, 0u};
+    if (tot) r = reserve_slots(a, ls, blockIdx.x % NQF, tot);
+    s_cnt[NW] = tot;
+    s_cnt[NW + 1] = r.q;
+    s_cnt[NW + 2] = r.pos;
+    s_cnt[NW + 3] = r.inseg;
+    s_cnt[NW + 4] = r.obase;
+  }
+  __syncthreads();
+  if (s_cnt[NW] == 0) return;
+  const Reserve r{s_cnt[NW + 1], s_cnt[NW + 2], s_cnt[NW + 3], s_cnt[NW + 4]};
+  uint32_t off = 0;
+  for (int w = 0; w < wave; ++w) off += s_cnt[w];
+  for (uint32_t i = lane; i < s.cnt; i += 64) put_slot(a, fout, r, off + i, s.buf[i]);
+  s.cnt = 0;
+}
+
+// ------------------------------------------------------------ child body
 template <int P>
 __device__ __forceinline__ bool visit(const Args& a, int32_t v, uint32_t wgt, uint32_t du,
                                       uint32_t L) {
@@ -114,18 +175,18 @@ __device__ __forceinline__ bool visit(const Args& a, int32_t v, uint32_t wgt, ui
     return false;
   }
   if (P == PROB_BFS) {
-    uint32_t word = (uint32_t)v >> 5, bit = 1u << (v & 31);
+    const uint32_t word = (uint32_t)v >> 5, bit = 1u << (v & 31);
     if (a.visit[word] & bit) return false;
-    uint32_t old = atomicOr(&a.visit[word], bit);
+    const uint32_t old = atomicOr(&a.visit[word], bit);
     if (old & bit) return false;
     a.level[v] = (int32_t)(L + 1);
     return true;
   } else {
-    uint32_t nd = du + wgt;
+    const uint32_t nd = du + wgt;
     if (nd >= a.dist[v]) return false;
-    uint32_t old = atomicMin(&a.dist[v], nd);
+    const uint32_t old = atomicMin(&a.dist[v], nd);
     if (nd >= old) return false;
-    uint32_t it = L + 1;
+    const uint32_t it = L + 1;
     if (a.visit[v] == it) return false;
     return atomicExch(&a.visit[v], it) != it;
   }
@@ -135,8 +196,8 @@ __device__ __forceinline__ bool visit(const Args& a, int32_t v, uint32_t wgt, ui
 // neighbours.  Wave-uniform loop so that appends stay wave-aggregated.
 template <int P>
 __device__ __forceinline__ void serial_children(const Args& a, int32_t start, int32_t cnt,
-                                                uint32_t du, uint32_t L, Stage& s, int32_t* fout,
-                                                uint32_t* fcount, int lane) {
+                                                uint32_t du, uint32_t L, Stage& s, LevelSet* ls,
+                                                int32_t* fout, int lane) {
   constexpr int U = 4;
   int32_t e = start;
   const int32_t end = start + cnt;
@@ -152,324 +213,284 @@ __device__ __forceinline__ void serial_children(const Args& a, int32_t start, in
     for (int r = 0; r < U; ++r) {
       bool f = false;
       if (v[r] >= 0) f = visit<P>(a, v[r], w[r], du, L);
-      stage_push(s, f, v[r], a, fout, fcount, lane);
+      stage_push(s, f, v[r], a, ls, fout, lane);
     }
     e += U;
   }
 }
 
-// Wait until descriptor p of this level is published; returns its child-block
-// base, or UINT32_MAX after the watchdog fired.
-__device__ __forceinline__ uint32_t desc_base(const Args& a, uint32_t p, uint32_t L) {
-  unsigned long long b = __hip_atomic_load(&a.desc_b[p], __ATOMIC_ACQUIRE, AGENT);
-  if ((uint32_t)(b >> 32) == L + 1) return (uint32_t)b;
-  const uint64_t t0 = now_ticks();
-  for (;;) {
-    __builtin_amdgcn_s_sleep(1);
-    b = __hip_atomic_load(&a.desc_b[p], __ATOMIC_ACQUIRE, AGENT);
-    if ((uint32_t)(b >> 32) == L + 1) return (uint32_t)b;
-    if (now_ticks() - t0 > a.watchdog_ticks) {
-      set_error(a.st, ERR_TIMEOUT);
-      return UINT32_MAX;
-    }
-  }
+// Per-workgroup counters: one row per workgroup, summed on the host.
+__device__ void add_stats(const Args& a, unsigned long long* s_stats, const uint32_t* v, int tid) {
+  if (!a.count_stats) return;
+  for (int k = 0; k < NSTAT; ++k)
+    if (v[k]) atomicAdd(&s_stats[k], (unsigned long long)v[k]);
+  __syncthreads();
+  if (tid < NSTAT && blockIdx.x < MAX_GRID) a.stats[blockIdx.x * NSTAT + tid] += s_stats[tid];
 }
 
-struct Claim {
-  int32_t start, deg, j;
-  uint32_t du;
-  int32_t quit;
-};
-
-// Wave 0 of a consumer workgroup: take a child-block ticket, wait for it to be
-// published, and disaggregate it (Sec. V-A: binary search of the scanned grid
-// sizes), here as 64-ary wave searches over descriptors, then records.
-template <int G, int CF>
-__device__ Claim claim_child(const Args& a, Ctr* c, uint32_t L, uint32_t ngroups, int lane) {
-  Claim r{0, 0, 0, 0u, 1};
-  uint32_t t = 0;
-  if (lane == 0) t = atomicAdd(&c->child_ticket, 1u);
-  t = __shfl(t, 0, 64);
-  unsigned long long dc = __hip_atomic_load(&c->desc_ctr, __ATOMIC_RELAXED, AGENT);
-  if (t >= (uint32_t)dc) {
-    const uint64_t t0 = now_ticks();
-    for (;;) {
-      uint32_t gf = __hip_atomic_load(&c->groups_finished, __ATOMIC_ACQUIRE, AGENT);
-      dc = __hip_atomic_load(&c->desc_ctr, __ATOMIC_RELAXED, AGENT);
-      if (t < (uint32_t)dc) break;
-      if (gf >= ngroups) return r;  // every group finished and t is past the end
-      if (now_ticks() - t0 > a.watchdog_ticks) {
-        set_error(a.st, ERR_TIMEOUT);
-        return r;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  // descriptor search: largest d with base(d) <= t; bases grow with d
-  const uint32_t ndesc = (uint32_t)(dc >> 32);
-  uint32_t lo = 0, hi = ndesc;
-  while (hi - lo > 1) {
-    const uint32_t step = (hi - lo + 63) / 64;
-    const uint32_t p = lo + (uint32_t)lane * step;
-    const uint32_t b = (p < hi) ? desc_base(a, p, L) : 0u;
-    if (__any(p < hi && b == UINT32_MAX)) return r;  // watchdog fired
-    const bool le = p < hi && b <= t;
-    const uint32_t k = (uint32_t)__popcll(__ballot(le));
-    lo += (k - 1) * step;
-    hi = min(lo + step, hi);
-  }
-  const uint32_t d = lo;
-  const uint32_t base = desc_base(a, d, L);
-  if (base == UINT32_MAX || d >= (uint32_t)a.desc_cap) return r;
-  const unsigned long long da = a.desc_a[d];
-  const uint32_t rec_base = (uint32_t)da, nrec = (uint32_t)(da >> 32);
-  const uint32_t tt = t - base;
-  if (nrec == 0 || (uint64_t)rec_base + nrec > (uint64_t)a.n) {
-    if (lane == 0) set_error(a.st, ERR_CAPACITY);
-    return r;
-  }
-  // record search: largest q with off(q) <= tt; offsets strictly increase
-  lo = 0;
-  hi = nrec;
-  while (hi - lo > 1) {
-    const uint32_t step = (hi - lo + 63) / 64;
-    const uint32_t p = lo + (uint32_t)lane * step;
-    bool le = false;
-    if (p < hi) le = (uint32_t)a.rec[rec_base + p].z <= tt;
-    const uint32_t k = (uint32_t)__popcll(__ballot(le));
-    lo += (k - 1) * step;
-    hi = min(lo + step, hi);
-  }
-  const int4 rc = a.rec[rec_base + lo];
-  r.start = rc.x;
-  r.deg = rc.y;
-  r.j = (int32_t)(tt - (uint32_t)rc.z);
-  r.du = (uint32_t)rc.w;
-  const int32_t gdim = (rc.y + a.CB - 1) / a.CB;
-  if (rc.y <= 0 || rc.x < 0 || (int64_t)rc.x + rc.y > (int64_t)a.m || r.j < 0 ||
-      r.j >= (gdim + CF - 1) / CF) {
-    if (lane == 0) set_error(a.st, ERR_CAPACITY);
-    return r;
-  }
-  r.quit = 0;
-  return r;
-}
-
-// Publish one aggregated child grid: records [rec_base, rec_base + nrec) with
-// `total` coarsened child blocks.  Called by one lane.
-__device__ __forceinline__ void publish(const Args& a, Ctr* c, uint32_t rec_base, uint32_t nrec,
-                                        uint32_t total, uint32_t L) {
+// Append one aggregated grid to descriptor queue q (one lane).
+__device__ __forceinline__ void publish(const Args& a, LevelSet* ls, uint32_t q, uint32_t rec_base,
+                                        uint32_t nrec, uint32_t total) {
   const unsigned long long old =
-      atomicAdd(&c->desc_ctr, ((unsigned long long)1 << 32) | (unsigned long long)total);
-  const uint32_t d = (uint32_t)(old >> 32), base = (uint32_t)old;
+      atomicAdd(&ls->qctr[q], ((unsigned long long)1 << 32) | (unsigned long long)total);
+  const uint32_t d = (uint32_t)(old >> 32);
   if (d >= (uint32_t)a.desc_cap) {
     set_error(a.st, ERR_CAPACITY);
     return;
   }
-  a.desc_a[d] = ((unsigned long long)nrec << 32) | rec_base;
-  __hip_atomic_store(&a.desc_b[d], ((unsigned long long)(L + 1) << 32) | base, __ATOMIC_RELEASE,
-                     AGENT);
+  a.desc[(size_t)q * a.desc_cap + d] = make_int4((int32_t)rec_base, (int32_t)nrec, (int32_t)old, 0);
 }
 
-enum { S_FRONT = 0, S_SERIAL, S_REC, S_CHILD, S_ESER, S_ECHILD, S_DESC, S_N };
-
-template <int P, int G, int CF>
-__global__ __launch_bounds__(PB) void step_kernel(Args a) {
+// ------------------------------------------------------------ parent kernel
+template <int P, int G>
+__global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
+  __shared__ uint32_t s_fpre[NQF + 2];
   __shared__ uint32_t s_scan[2 * NW];
-  __shared__ uint32_t s_bc[4];
-  __shared__ Claim s_claim;
-  __shared__ unsigned long long s_stats[S_N];
+  __shared__ uint32_t s_bc[NW + 8];
+  __shared__ unsigned long long s_stats[NSTAT];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
   if (st->done || st->error) return;
-  const uint32_t L = st->level;
-  const uint32_t F = st->fcount[L % 3];
-  if (F == 0) return;
-  const uint32_t cur = L % 3, nxt = (L + 1) % 3, nn = (L + 2) % 3;
-  Ctr* c = &st->ctr[cur];
+  const uint32_t L = st->base + step;
+  LevelSet* prv = &st->set[(L + 2) % 3];  // fills of frontier L
+  LevelSet* cur = &st->set[L % 3];        // this level: next-frontier fills, queues, groups
   const int32_t* fin = (L & 1) ? a.front1 : a.front0;
   int32_t* fout = (L & 1) ? a.front0 : a.front1;
-  uint32_t* fcount = &st->fcount[nxt];
 
-  // Counters of the following step are idle now: clear them here.
-  if (blockIdx.x == 0 && tid == 0) {
-    Ctr* z = &st->ctr[nxt];
-    z->parent_claim = 0;
-    z->child_ticket = 0;
-    z->groups_finished = 0;
-    z->exit_count = 0;
-    z->desc_ctr = 0;
-    st->fcount[nn] = 0;
+  // frontier L = queues 0..NQF-1 then overflow; prefix of their fills
+  if (wave == 0) {
+    const uint32_t c = min(prv->fcnt[lane], (uint32_t)a.fcap);
+    const uint32_t incl = wave_incl_scan(c, lane);
+    s_fpre[lane + 1] = incl;
+    if (lane == 0) s_fpre[0] = 0;
+    if (lane == 63) s_fpre[NQF + 1] = incl + prv->fcnt[NQF];
+  }
+  if (tid < NSTAT) s_stats[tid] = 0;
+  __syncthreads();
+  const uint32_t F = s_fpre[NQF + 1];
+  if (F == 0) {
+    if (blockIdx.x == 0 && tid == 0) st->done = 1;
+    return;
+  }
+  if (blockIdx.x == 0) {
+    LevelSet* z = &st->set[(L + 1) % 3];  // idle until level L + 1
+    if (tid <= NQF) z->fcnt[tid] = 0;
+    if (tid < NQD) z->qctr[tid] = 0;
+    if (tid == 0) st->levels_run = L + 1;
   }
   if (G == AGG_MULTI) {
+    const uint32_t nz = (L + 1) % 3;
     for (int i = blockIdx.x * PB + tid; i < a.ngroups_cap; i += gridDim.x * PB) {
-      a.grp_packed[nxt * a.ngroups_cap + i] = 0;
-      a.grp_done[nxt * a.ngroups_cap + i] = 0;
+      a.grp_packed[nz * a.ngroups_cap + i] = 0;
+      a.grp_done[nz * a.ngroups_cap + i] = 0;
     }
   }
-  if (tid < S_N) s_stats[tid] = 0;
-  __syncthreads();
 
   Stage s{s_stage[wave], 0u};
-  uint32_t n_front = 0, n_serial = 0, n_rec = 0, n_desc = 0, n_child = 0;
-  uint64_t e_serial = 0, e_child = 0;
-
-  const uint32_t nvb = (F + PB - 1) / PB;
-  if (G == AGG_FLAT) {
-    // No nesting: thread per frontier vertex, serial neighbour loop.
-    for (uint32_t i0 = blockIdx.x * PB; i0 < F; i0 += gridDim.x * PB) {
-      const uint32_t i = i0 + tid;
-      int32_t start = 0, deg = 0;
-      uint32_t du = 0;
-      if (i < F) {
-        const int32_t u = fin[i];
-        start = a.rp[u];
-        deg = a.rp[u + 1] - start;
-        if (P == PROB_SSSP) du = a.dist[u];
-        ++n_front;
-        if (deg > 0) { ++n_serial; e_serial += deg; }
+  uint32_t sv[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const uint32_t nvb = ceil_div(F, PB);
+  for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const uint32_t i = vb * PB + tid;
+    int32_t start = 0, deg = 0;
+    uint32_t du = 0;
+    if (i < F) {
+      uint32_t lo = 0, hi = NQF + 1;  // queue of entry i: s_fpre[q] <= i < s_fpre[q + 1]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_fpre[mid] <= i) lo = mid; else hi = mid;
       }
-      serial_children<P>(a, start, deg, du, L, s, fout, fcount, lane);
+      const int32_t u = fin[(size_t)lo * a.fcap + (i - s_fpre[lo])];
+      start = a.rp[u];
+      deg = a.rp[u + 1] - start;
+      if (P == PROB_SSSP) du = a.dist[u];
+      ++sv[S_FRONT];
     }
-  } else {
-    const uint32_t ngroups = (G == AGG_MULTI) ? (nvb + a.k - 1) / a.k : nvb;
-    // ---------------- parent phase: claim virtual parent blocks
-    for (;;) {
-      if (tid == 0) s_bc[0] = atomicAdd(&c->parent_claim, 1u);
-      __syncthreads();
-      const uint32_t vb = s_bc[0];
-      __syncthreads();
-      if (vb >= nvb) break;
-      const uint32_t i = vb * PB + tid;
-      int32_t start = 0, deg = 0;
-      uint32_t du = 0;
-      if (i < F) {
-        const int32_t u = fin[i];
-        start = a.rp[u];
-        deg = a.rp[u + 1] - start;
-        if (P == PROB_SSSP) du = a.dist[u];
-        ++n_front;
-      }
-      const bool launch = deg > 0 && deg >= a.T;
-      const bool ser = deg > 0 && !launch;
-      if (ser) { ++n_serial; e_serial += deg; }
-      // thresholded children run in the parent (Sec. III-B)
-      serial_children<P>(a, start, ser ? deg : 0, du, L, s, fout, fcount, lane);
-      // coarsened grid size (Sec. IV-B)
-      const uint32_t gdim = launch ? (uint32_t)((deg + a.CB - 1) / a.CB) : 0u;
-      const uint32_t cg = (gdim + CF - 1) / CF;
-      if (launch) ++n_rec;
+    if (G == AGG_FLAT) {
+      if (deg > 0) { ++sv[S_SERIAL]; sv[S_ESER] += deg; }
+      serial_children<P>(a, start, deg, du, L, s, cur, fout, lane);
+      continue;
+    }
+    const bool launch = deg > 0 && deg >= a.T;
+    const bool ser = deg > 0 && !launch;
+    if (ser) { ++sv[S_SERIAL]; sv[S_ESER] += deg; }
+    // thresholded children run in the parent (Sec. III-B)
+    serial_children<P>(a, start, ser ? deg : 0, du, L, s, cur, fout, lane);
+    // coarsened grid size (Sec. IV-B)
+    const uint32_t gdim = launch ? ceil_div((uint32_t)deg, (uint32_t)a.CB) : 0u;
+    const uint32_t cg = ceil_div(gdim, (uint32_t)a.CF);
+    if (launch) ++sv[S_REC];
 
-      if (G == AGG_NONE) {
-        // one grid per launching parent
-        if (launch) {
-          const unsigned long long old =
-              atomicAdd(&c->desc_ctr, ((unsigned long long)1 << 32) | (unsigned long long)cg);
-          const uint32_t d = (uint32_t)(old >> 32), base = (uint32_t)old;
-          if (d < (uint32_t)a.desc_cap) {
-            a.rec[d] = make_int4(start, deg, 0, (int32_t)du);
-            a.desc_a[d] = ((unsigned long long)1 << 32) | d;
-            __hip_atomic_store(&a.desc_b[d], ((unsigned long long)(L + 1) << 32) | base,
-                               __ATOMIC_RELEASE, AGENT);
-            ++n_desc;
-          } else {
-            set_error(st, ERR_CAPACITY);
-          }
+    if (G == AGG_NONE) {
+      // every launching parent publishes its own grid; its record sits at its
+      // frontier index
+      if (launch) {
+        a.rec[i] = make_int4(start, deg, 0, (int32_t)du);
+        publish(a, cur, vb % NQD, i, 1u, cg);
+        ++sv[S_DESC];
+      }
+    } else if (G == AGG_WAVE) {
+      const unsigned long long m = __ballot(launch);
+      if (m) {  // wave-uniform
+        const uint32_t incl = wave_incl_scan(cg, lane);
+        const uint32_t total = __shfl(incl, 63, 64);
+        const uint32_t seg = vb * PB + wave * 64;
+        if (launch)
+          a.rec[seg + lane_rank(m)] = make_int4(start, deg, (int32_t)(incl - cg), (int32_t)du);
+        if (lane == 0) {
+          publish(a, cur, vb % NQD, seg, (uint32_t)__popcll(m), total);
+          ++sv[S_DESC];
         }
-        __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(&c->groups_finished, 1u, __ATOMIC_RELEASE, AGENT);
-      } else if (G == AGG_WAVE) {
-        const unsigned long long m = __ballot(launch);
-        if (m) {
-          const uint32_t nrec = (uint32_t)__popcll(m);
-          const uint32_t incl = wave_incl_scan(launch ? cg : 0u, lane);
-          const uint32_t total = __shfl(incl, 63, 64);
-          const uint32_t seg = vb * PB + wave * 64;
-          if (launch)
-            a.rec[seg + lane_rank(m)] = make_int4(start, deg, (int32_t)(incl - cg), (int32_t)du);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          if (lane == 0) { publish(a, c, seg, nrec, total, L); ++n_desc; }
-        }
-        __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(&c->groups_finished, 1u, __ATOMIC_RELEASE, AGENT);
-      } else {
-        // block-level scan of (launch, cg): wave scans, then across waves in LDS
-        const unsigned long long m = __ballot(launch);
-        const uint32_t incl = wave_incl_scan(launch ? cg : 0u, lane);
-        if (lane == 63) {
-          s_scan[wave] = (uint32_t)__popcll(m);
-          s_scan[NW + wave] = incl;
-        }
-        __syncthreads();
-        uint32_t roff = 0, coff = 0, nrec_b = 0, total_b = 0;
+      }
+    } else {
+      // block-level scan of (launch, cg): wave scans, then across waves in LDS
+      const unsigned long long m = __ballot(launch);
+      const uint32_t incl = wave_incl_scan(cg, lane);
+      if (lane == 63) {
+        s_scan[wave] = (uint32_t)__popcll(m);
+        s_scan[NW + wave] = incl;
+      }
+      __syncthreads();
+      uint32_t roff = 0, coff = 0, nrec_b = 0, total_b = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          if (w < wave) { roff += s_scan[w]; coff += s_scan[NW + w]; }
-          nrec_b += s_scan[w];
-          total_b += s_scan[NW + w];
+      for (int w = 0; w < NW; ++w) {
+        if (w < wave) { roff += s_scan[w]; coff += s_scan[NW + w]; }
+        nrec_b += s_scan[w];
+        total_b += s_scan[NW + w];
+      }
+      if (G == AGG_BLOCK) {
+        const uint32_t seg = vb * PB;
+        if (launch)
+          a.rec[seg + roff + lane_rank(m)] =
+              make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
+        if (tid == 0 && nrec_b) {
+          publish(a, cur, vb % NQD, seg, nrec_b, total_b);
+          ++sv[S_DESC];
         }
-        if (G == AGG_BLOCK) {
-          const uint32_t seg = vb * PB;
-          if (launch)
-            a.rec[seg + roff + lane_rank(m)] =
-                make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          __syncthreads();
-          if (tid == 0) {
-            if (nrec_b) { publish(a, c, seg, nrec_b, total_b, L); ++n_desc; }
-            __hip_atomic_fetch_add(&c->groups_finished, 1u, __ATOMIC_RELEASE, AGENT);
-          }
-        } else {  // AGG_MULTI: group of k virtual blocks (Sec. V-A)
-          const uint32_t g = vb / (uint32_t)a.k;
-          const uint32_t seg = g * (uint32_t)a.k * PB;
-          unsigned long long* gp = &a.grp_packed[cur * a.ngroups_cap + g];
-          uint32_t* gd = &a.grp_done[cur * a.ngroups_cap + g];
-          if (tid == 0) {
-            unsigned long long old = 0;
-            if (nrec_b)
-              old = atomicAdd(gp, ((unsigned long long)nrec_b << 32) | (unsigned long long)total_b);
-            s_bc[1] = (uint32_t)(old >> 32);
-            s_bc[2] = (uint32_t)old;
-          }
-          __syncthreads();
-          const uint32_t slot0 = s_bc[1], off0 = s_bc[2];
-          if (launch)
-            a.rec[seg + slot0 + roff + lane_rank(m)] =
-                make_int4(start, deg, (int32_t)(off0 + coff + incl - cg), (int32_t)du);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          __syncthreads();
-          if (tid == 0) {
-            const uint32_t in_group = min((uint32_t)a.k, nvb - g * (uint32_t)a.k);
-            const uint32_t done = __hip_atomic_fetch_add(gd, 1u, __ATOMIC_ACQ_REL, AGENT);
-            if (done == in_group - 1) {
-              const unsigned long long tot = __hip_atomic_load(gp, __ATOMIC_RELAXED, AGENT);
-              const uint32_t nrec_g = (uint32_t)(tot >> 32);
-              if (nrec_g) { publish(a, c, seg, nrec_g, (uint32_t)tot, L); ++n_desc; }
-              __hip_atomic_fetch_add(&c->groups_finished, 1u, __ATOMIC_RELEASE, AGENT);
+        __syncthreads();  // s_scan reuse
+      } else {  // AGG_MULTI: group of k consecutive virtual blocks (Sec. V-A)
+        const uint32_t g = vb / (uint32_t)a.k;
+        const uint32_t seg = g * (uint32_t)a.k * PB;
+        unsigned long long* gp = &a.grp_packed[(L % 3) * a.ngroups_cap + g];
+        uint32_t* gd = &a.grp_done[(L % 3) * a.ngroups_cap + g];
+        if (tid == 0) {
+          unsigned long long old = 0;
+          if (nrec_b)
+            old = atomicAdd(gp, ((unsigned long long)nrec_b << 32) | (unsigned long long)total_b);
+          s_bc[0] = (uint32_t)(old >> 32);
+          s_bc[1] = (uint32_t)old;
+        }
+        __syncthreads();
+        const uint32_t slot0 = s_bc[0], off0 = s_bc[1];
+        if (launch)
+          a.rec[seg + slot0 + roff + lane_rank(m)] =
+              make_int4(start, deg, (int32_t)(off0 + coff + incl - cg), (int32_t)du);
+        if (tid == 0) {
+          // the group's last block to finish "launches" the aggregated grid;
+          // its packed-counter add returned before this increment was issued
+          const uint32_t in_group = min((uint32_t)a.k, nvb - g * (uint32_t)a.k);
+          const uint32_t done = atomicAdd(gd, 1u);
+          if (done == in_group - 1) {
+            const unsigned long long tot = atomicAdd(gp, 0ull);
+            const uint32_t nrec_g = (uint32_t)(tot >> 32);
+            if (nrec_g) {
+              publish(a, cur, g % NQD, seg, nrec_g, (uint32_t)tot);
+              ++sv[S_DESC];
             }
           }
         }
+        __syncthreads();  // s_scan / s_bc reuse
       }
     }
+  }
+  block_flush(s, a, cur, fout, tid, s_bc);
+  add_stats(a, s_stats, sv, tid);
+}
 
-    // ---------------- child phase: consume aggregated child grids
-    for (;;) {
-      if (wave == 0) {
-        Claim cl = claim_child<G, CF>(a, c, L, ngroups, lane);
-        if (lane == 0) s_claim = cl;
+// ------------------------------------------------------------ child kernel
+struct Cursor {
+  uint32_t q, d, r, j;   // queue, descriptor, record within descriptor, block within record
+  uint32_t rec_base, nrec;
+};
+
+// Largest p in [0, n) with key(p) <= t, where key(0) <= t and keys increase:
+// 64-ary wave search (each round narrows the range 64-fold).
+template <typename KeyFn>
+__device__ __forceinline__ uint32_t wave_upper_search(uint32_t n, uint32_t t, int lane, KeyFn key) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t p = lo + (uint32_t)lane * step;
+    const bool le = p < hi && key(p) <= t;
+    const uint32_t k = (uint32_t)__popcll(__ballot(le));
+    lo += (k - 1) * step;
+    hi = min(lo + step, hi);
+  }
+  return lo;
+}
+
+template <int P, int CF>
+__global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
+  __shared__ int32_t s_stage[NW][STAGE];
+  __shared__ uint32_t s_bc[NW + 8];
+  __shared__ unsigned long long s_stats[NSTAT];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  State* st = a.st;
+  if (st->done || st->error) return;
+  const uint32_t L = st->base + step;
+  LevelSet* cur = &st->set[L % 3];
+  int32_t* fout = (L & 1) ? a.front0 : a.front1;
+
+  // aggregated child blocks of this level, queue by queue
+  uint32_t qpre[NQD + 1];
+  uint32_t qnd[NQD];
+  qpre[0] = 0;
+#pragma unroll
+  for (int q = 0; q < NQD; ++q) {
+    const unsigned long long c = cur->qctr[q];
+    qnd[q] = (uint32_t)(c >> 32);
+    qpre[q + 1] = qpre[q] + (uint32_t)c;
+  }
+  const uint32_t B = qpre[NQD];
+  if (B == 0) return;
+  const uint32_t t0 = (uint32_t)((uint64_t)blockIdx.x * B / gridDim.x);
+  const uint32_t t1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * B / gridDim.x);
+  if (tid < NSTAT) s_stats[tid] = 0;
+  __syncthreads();
+  uint32_t sv[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+  Stage s{s_stage[wave], 0u};
+
+  if (t0 < t1) {
+    // disaggregation of the first block (Sec. V-A): queue, descriptor, record
+    Cursor c{0, 0, 0, 0, 0, 0};
+    while (t0 >= qpre[c.q + 1]) ++c.q;
+    const int4* dq = a.desc + (size_t)c.q * a.desc_cap;
+    const uint32_t tq = t0 - qpre[c.q];
+    c.d = wave_upper_search(qnd[c.q], tq, lane, [&](uint32_t p) { return (uint32_t)dq[p].z; });
+    int4 dd = dq[c.d];
+    c.rec_base = (uint32_t)dd.x;
+    c.nrec = (uint32_t)dd.y;
+    const uint32_t tr = tq - (uint32_t)dd.z;
+    c.r = wave_upper_search(c.nrec, tr, lane,
+                            [&](uint32_t p) { return (uint32_t)a.rec[c.rec_base + p].z; });
+    int4 rc = a.rec[c.rec_base + c.r];
+    c.j = tr - (uint32_t)rc.z;
+    const int32_t CB = a.CB;
+    for (uint32_t t = t0;;) {
+      const int32_t start = rc.x, deg = rc.y;
+      const uint32_t cgr = ceil_div(ceil_div((uint32_t)deg, (uint32_t)CB), (uint32_t)CF);
+      if (deg <= 0 || start < 0 || (int64_t)start + deg > (int64_t)a.m || c.j >= cgr) {
+        if (tid == 0) set_error(st, ERR_CAPACITY);
+        break;
       }
-      __syncthreads();
-      const Claim cl = s_claim;
-      __syncthreads();
-      if (cl.quit) break;
-      if (tid == 0) ++n_child;
+      if (tid == 0) ++sv[S_CHILD];
       // coarsening loop (Sec. IV-B): original blocks j*CF .. j*CF+CF-1 of CB
       // lanes cover the contiguous edge range [j*CF*CB, (j+1)*CF*CB)
-      const int32_t base_idx = cl.j * CF * a.CB;
-      const int32_t lim = min(cl.deg - base_idx, CF * a.CB);
-      const int32_t e0 = cl.start + base_idx;
+      const int32_t base_idx = (int32_t)c.j * CF * CB;
+      const int32_t lim = min(deg - base_idx, CF * CB);
+      const int32_t e0 = start + base_idx;
       int32_t v[CF];
       uint32_t w[CF];
 #pragma unroll
@@ -483,41 +504,42 @@ __global__ __launch_bounds__(PB) void step_kernel(Args a) {
         if (r * PB < lim) {  // uniform across the workgroup
           bool f = false;
           if (v[r] >= 0) {
-            ++e_child;
-            f = visit<P>(a, v[r], w[r], cl.du, L);
+            ++sv[S_ECHILD];
+            f = visit<P>(a, v[r], w[r], (uint32_t)rc.w, L);
           }
-          stage_push(s, f, v[r], a, fout, fcount, lane);
+          stage_push(s, f, v[r], a, cur, fout, lane);
         }
+      }
+      if (++t >= t1) break;
+      // advance to the next aggregated child block
+      if (++c.j == cgr) {
+        c.j = 0;
+        if (++c.r == c.nrec) {
+          c.r = 0;
+          if (++c.d == qnd[c.q]) {
+            c.d = 0;
+            do { ++c.q; } while (c.q < NQD && qnd[c.q] == 0);
+            if (c.q >= NQD) {
+              if (tid == 0) set_error(st, ERR_CAPACITY);
+              break;
+            }
+            dq = a.desc + (size_t)c.q * a.desc_cap;
+          }
+          dd = dq[c.d];
+          c.rec_base = (uint32_t)dd.x;
+          c.nrec = (uint32_t)dd.y;
+        }
+        rc = a.rec[c.rec_base + c.r];
       }
     }
   }
-
-  // ---------------- step end
-  stage_flush(s, a, fout, fcount, lane);
-  if (a.count_stats) {
-    atomicAdd(&s_stats[S_FRONT], (unsigned long long)n_front);
-    atomicAdd(&s_stats[S_SERIAL], (unsigned long long)n_serial);
-    atomicAdd(&s_stats[S_REC], (unsigned long long)n_rec);
-    atomicAdd(&s_stats[S_CHILD], (unsigned long long)n_child);
-    atomicAdd(&s_stats[S_ESER], (unsigned long long)e_serial);
-    atomicAdd(&s_stats[S_ECHILD], (unsigned long long)e_child);
-    atomicAdd(&s_stats[S_DESC], (unsigned long long)n_desc);
-  }
-  __syncthreads();
-  if (a.count_stats && tid < S_N && s_stats[tid]) atomicAdd(&st->stats[tid], s_stats[tid]);
-  if (tid == 0) {
-    const uint32_t old = __hip_atomic_fetch_add(&c->exit_count, 1u, __ATOMIC_ACQ_REL, AGENT);
-    if (old == gridDim.x - 1) {
-      const uint32_t nf = __hip_atomic_load(fcount, __ATOMIC_RELAXED, AGENT);
-      st->levels_run = L + 1;
-      st->level = L + 1;
-      if (nf == 0) st->done = 1;
-    }
-  }
+  block_flush(s, a, cur, fout, tid, s_bc);
+  add_stats(a, s_stats, sv, tid);
 }
 
-// Traversal start: outputs to "unreached", visit words cleared, descriptor
-// flags cleared, counters zeroed, the source placed in frontier 0.
+// ------------------------------------------------------------ init / advance
+// Traversal start: outputs to "unreached", visit words and per-workgroup
+// counters cleared, level sets zeroed, the source alone in frontier 0.
 template <int P>
 __global__ __launch_bounds__(PB) void init_kernel(Args a, int32_t src) {
   const uint32_t gsz = gridDim.x * PB;
@@ -535,65 +557,62 @@ __global__ __launch_bounds__(PB) void init_kernel(Args a, int32_t src) {
     for (uint32_t i = gid; i < words; i += gsz)
       a.visit[i] = (i == (uint32_t)src >> 5) ? (1u << (src & 31)) : 0u;
   }
-  for (uint32_t i = gid; i < (uint32_t)a.desc_cap; i += gsz) a.desc_b[i] = 0;
   for (uint32_t i = gid; i < 3u * (uint32_t)a.ngroups_cap; i += gsz) {
     a.grp_packed[i] = 0;
     a.grp_done[i] = 0;
   }
-  if (gid == 0) {
-    State* st = a.st;
-    st->level = 0;
-    st->done = 0;
-    st->error = 0;
-    st->levels_run = 0;
-    st->fcount[0] = 1;
-    st->fcount[1] = 0;
-    st->fcount[2] = 0;
-    st->fcount[3] = 0;
-    for (int k = 0; k < 3; ++k) {
-      st->ctr[k].parent_claim = 0;
-      st->ctr[k].child_ticket = 0;
-      st->ctr[k].groups_finished = 0;
-      st->ctr[k].exit_count = 0;
-      st->ctr[k].desc_ctr = 0;
-    }
-    for (int k = 0; k < 8; ++k) st->stats[k] = 0;
-    a.front0[0] = src;
-  }
+  for (uint32_t i = gid; i < (uint32_t)(MAX_GRID * NSTAT); i += gsz) a.stats[i] = 0;
+  // frontier 0 = {src} in queue 0; its fill lives in the set of level -1 = set 2
+  const uint32_t src_fill =
+      (uint32_t)((__builtin_offsetof(State, set) + 2 * sizeof(LevelSet) +
+                  __builtin_offsetof(LevelSet, fcnt)) / 4);
+  uint32_t* stw = (uint32_t*)a.st;
+  for (uint32_t i = gid; i < sizeof(State) / 4; i += gsz) stw[i] = (i == src_fill) ? 1u : 0u;
+  if (gid == 0) a.front0[0] = src;
+}
+
+__global__ void advance_kernel(State* st, uint32_t steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->base += steps;
 }
 
 // ---------------------------------------------------------------- tables
-template <int P, int G>
-static const void* step_for_cf(int cf) {
-  switch (cf) {
-    case 1: return (const void*)step_kernel<P, G, 1>;
-    case 2: return (const void*)step_kernel<P, G, 2>;
-    case 4: return (const void*)step_kernel<P, G, 4>;
-    case 8: return (const void*)step_kernel<P, G, 8>;
-    case 16: return (const void*)step_kernel<P, G, 16>;
+template <int P>
+static const void* parent_for(int g) {
+  switch (g) {
+    case AGG_NONE: return (const void*)parent_kernel<P, AGG_NONE>;
+    case AGG_WAVE: return (const void*)parent_kernel<P, AGG_WAVE>;
+    case AGG_BLOCK: return (const void*)parent_kernel<P, AGG_BLOCK>;
+    case AGG_MULTI: return (const void*)parent_kernel<P, AGG_MULTI>;
+    case AGG_FLAT: return (const void*)parent_kernel<P, AGG_FLAT>;
     default: return nullptr;
   }
 }
 
 template <int P>
-static const void* step_for(int g, int cf) {
-  switch (g) {
-    case AGG_NONE: return step_for_cf<P, AGG_NONE>(cf);
-    case AGG_WAVE: return step_for_cf<P, AGG_WAVE>(cf);
-    case AGG_BLOCK: return step_for_cf<P, AGG_BLOCK>(cf);
-    case AGG_MULTI: return step_for_cf<P, AGG_MULTI>(cf);
-    case AGG_FLAT: return (const void*)step_kernel<P, AGG_FLAT, 1>;
+static const void* child_for(int cf) {
+  switch (cf) {
+    case 1: return (const void*)child_kernel<P, 1>;
+    case 2: return (const void*)child_kernel<P, 2>;
+    case 4: return (const void*)child_kernel<P, 4>;
+    case 8: return (const void*)child_kernel<P, 8>;
+    case 16: return (const void*)child_kernel<P, 16>;
     default: return nullptr;
   }
 }
 
-const void* step_kernel_ptr(int problem, int gran, int cf) {
-  return problem == PROB_BFS ? step_for<PROB_BFS>(gran, cf) : step_for<PROB_SSSP>(gran, cf);
+const void* parent_kernel_ptr(int problem, int gran) {
+  return problem == PROB_BFS ? parent_for<PROB_BFS>(gran) : parent_for<PROB_SSSP>(gran);
+}
+
+const void* child_kernel_ptr(int problem, int cf) {
+  return problem == PROB_BFS ? child_for<PROB_BFS>(cf) : child_for<PROB_SSSP>(cf);
 }
 
 const void* init_kernel_ptr(int problem) {
   return problem == PROB_BFS ? (const void*)init_kernel<PROB_BFS>
                              : (const void*)init_kernel<PROB_SSSP>;
 }
+
+const void* advance_kernel_ptr() { return (const void*)advance_kernel; }
 
 }  // namespace dpo
