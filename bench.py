@@ -58,7 +58,7 @@ def agg_of(s):
 
 
 # Best point of the config-2 sweep on MI355X; overridable.
-TUNED = {"bfs22": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
+TUNED = {"bfs22": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4)}
 

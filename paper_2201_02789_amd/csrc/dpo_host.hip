@@ -195,13 +195,13 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid
   hipGraphExec_t exec;
   if (s == DPO_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
     s = DPO_ERR_HIP;
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (s != DPO_OK) return s;
   if ((int)r.graphs.size() >= kMaxCachedGraphs) {
     size_t victim = 0;
     for (size_t i = 1; i < r.graphs.size(); ++i)
       if (r.graphs[i].last_use < r.graphs[victim].last_use) victim = i;
-    hipGraphExecDestroy(r.graphs[victim].exec);
+    (void)hipGraphExecDestroy(r.graphs[victim].exec);
     r.graphs.erase(r.graphs.begin() + victim);
   }
   r.graphs.push_back(CachedGraph{parent, child, pgrid, cgrid, steps, args, exec, ++r.tick});

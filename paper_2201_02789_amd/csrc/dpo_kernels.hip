@@ -114,7 +114,7 @@ struct Stage {
 };
 
 // Flush one wave's staged vertices (wave-uniform call).
-__device__ __noinline__ void stage_flush(Stage& s, const Args& a, LevelSet* ls, int32_t* fout,
+__device__ __forceinline__ void stage_flush(Stage& s, const Args& a, LevelSet* ls, int32_t* fout,
                                          int lane) {
   if (s.cnt == 0) return;
   Reserve r{0u, 0u, 0u, 0u};
@@ -141,7 +141,7 @@ __device__ __forceinline__ void stage_push(Stage& s, bool found, int32_t v, cons
 }
 
 // End of kernel: one reservation for the whole workgroup.  Block-uniform call.
-__device__ void block_flush(Stage& s, const Args& a, LevelSet* ls, int32_t* fout, int tid,
+__device__ __forceinline__ void block_flush(Stage& s, const Args& a, LevelSet* ls, int32_t* fout, int tid,
                             uint32_t* s_cnt /* LDS [NW + 5] */) {
   const int lane = tid & 63, wave = tid >> 6;
   if (lane == 0) s_cnt[wave] = s.cnt;
@@ -167,63 +167,109 @@ __device__ void block_flush(Stage& s, const Args& a, LevelSet* ls, int32_t* fout
 }
 
 // ------------------------------------------------------------ child body
-template <int P>
-__device__ __forceinline__ bool visit(const Args& a, int32_t v, uint32_t wgt, uint32_t du,
-                                      uint32_t L) {
-  if ((uint32_t)v >= (uint32_t)a.n) {
-    set_error(a.st, ERR_ARG);
-    return false;
+// The child body for U neighbours of one lane at a time: all probes are
+// issued before any atomic, so the U memory round trips overlap.  BFS claims v
+// in the visited bitmap and writes level[v] = L + 1; SSSP relaxes dist[v] with
+// atomicMin and queues v once per iteration through its stamp.
+template <int P, int U>
+__device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U],
+                                            const uint32_t (&w)[U], const uint32_t (&du)[U],
+                                            uint32_t L, bool (&f)[U]) {
+  bool ok[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    ok[u] = v[u] >= 0;
+    if (ok[u] && (uint32_t)v[u] >= (uint32_t)a.n) {
+      set_error(a.st, ERR_ARG);
+      ok[u] = false;
+    }
+    f[u] = false;
   }
   if (P == PROB_BFS) {
-    const uint32_t word = (uint32_t)v >> 5, bit = 1u << (v & 31);
-    if (a.visit[word] & bit) return false;
-    const uint32_t old = atomicOr(&a.visit[word], bit);
-    if (old & bit) return false;
-    a.level[v] = (int32_t)(L + 1);
-    return true;
+    uint32_t word[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) word[u] = ok[u] ? a.visit[(uint32_t)v[u] >> 5] : ~0u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t bit = 1u << (v[u] & 31);
+      if (ok[u] && !(word[u] & bit)) word[u] = atomicOr(&a.visit[(uint32_t)v[u] >> 5], bit);
+      else word[u] = ~0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      f[u] = !(word[u] & (1u << (v[u] & 31)));
+      if (f[u]) a.level[v[u]] = (int32_t)(L + 1);
+    }
   } else {
-    const uint32_t nd = du + wgt;
-    if (nd >= a.dist[v]) return false;
-    const uint32_t old = atomicMin(&a.dist[v], nd);
-    if (nd >= old) return false;
+    uint32_t nd[U], cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      nd[u] = du[u] + w[u];
+      cur[u] = ok[u] ? a.dist[v[u]] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (ok[u] && nd[u] < cur[u]) cur[u] = atomicMin(&a.dist[v[u]], nd[u]);
+      else cur[u] = 0u;
+    }
     const uint32_t it = L + 1;
-    if (a.visit[v] == it) return false;
-    return atomicExch(&a.visit[v], it) != it;
+    uint32_t stamp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      f[u] = nd[u] < cur[u];  // improved
+      stamp[u] = f[u] ? a.visit[v[u]] : it;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (f[u] && stamp[u] != it) stamp[u] = atomicExch(&a.visit[v[u]], it);
+      else stamp[u] = it;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) f[u] = stamp[u] != it;
   }
 }
 
 // Serial version of the child (Sec. III-B): the parent lane walks its own
-// neighbours.  Wave-uniform loop so that appends stay wave-aggregated.
+// neighbours.  Wave-uniform loop so that appends stay wave-aggregated; U
+// neighbours in flight per lane.
 template <int P>
 __device__ __forceinline__ void serial_children(const Args& a, int32_t start, int32_t cnt,
                                                 uint32_t du, uint32_t L, Stage& s, LevelSet* ls,
                                                 int32_t* fout, int lane) {
-  constexpr int U = 4;
+  constexpr int U = 8;
   int32_t e = start;
   const int32_t end = start + cnt;
   while (__any(e < end)) {
     int32_t v[U];
-    uint32_t w[U];
+    uint32_t w[U], dus[U];
+    bool f[U];
 #pragma unroll
     for (int r = 0; r < U; ++r) {
       v[r] = (e + r < end) ? a.col[e + r] : -1;
       w[r] = (P == PROB_SSSP && e + r < end) ? a.w[e + r] : 0u;
+      dus[r] = du;
     }
+    visit_batch<P, U>(a, v, w, dus, L, f);
 #pragma unroll
-    for (int r = 0; r < U; ++r) {
-      bool f = false;
-      if (v[r] >= 0) f = visit<P>(a, v[r], w[r], du, L);
-      stage_push(s, f, v[r], a, ls, fout, lane);
-    }
+    for (int r = 0; r < U; ++r) stage_push(s, f[r], v[r], a, ls, fout, lane);
     e += U;
   }
 }
 
+struct Counters {
+  uint32_t front, serial, rec, child, eser, echild, desc;
+};
+
 // Per-workgroup counters: one row per workgroup, summed on the host.
-__device__ void add_stats(const Args& a, unsigned long long* s_stats, const uint32_t* v, int tid) {
+__device__ __forceinline__ void add_stats(const Args& a, unsigned long long* s_stats, const Counters& c, int tid) {
   if (!a.count_stats) return;
-  for (int k = 0; k < NSTAT; ++k)
-    if (v[k]) atomicAdd(&s_stats[k], (unsigned long long)v[k]);
+  if (c.front) atomicAdd(&s_stats[S_FRONT], (unsigned long long)c.front);
+  if (c.serial) atomicAdd(&s_stats[S_SERIAL], (unsigned long long)c.serial);
+  if (c.rec) atomicAdd(&s_stats[S_REC], (unsigned long long)c.rec);
+  if (c.child) atomicAdd(&s_stats[S_CHILD], (unsigned long long)c.child);
+  if (c.eser) atomicAdd(&s_stats[S_ESER], (unsigned long long)c.eser);
+  if (c.echild) atomicAdd(&s_stats[S_ECHILD], (unsigned long long)c.echild);
+  if (c.desc) atomicAdd(&s_stats[S_DESC], (unsigned long long)c.desc);
   __syncthreads();
   if (tid < NSTAT && blockIdx.x < MAX_GRID) a.stats[blockIdx.x * NSTAT + tid] += s_stats[tid];
 }
@@ -241,7 +287,21 @@ __device__ __forceinline__ void publish(const Args& a, LevelSet* ls, uint32_t q,
   a.desc[(size_t)q * a.desc_cap + d] = make_int4((int32_t)rec_base, (int32_t)nrec, (int32_t)old, 0);
 }
 
+// Frontier entry i of level L: queue q with s_fpre[q] <= i < s_fpre[q + 1].
+__device__ __forceinline__ int32_t frontier_at(const Args& a, const int32_t* fin,
+                                               const uint32_t* s_fpre, uint32_t i) {
+  uint32_t lo = 0, hi = NQF + 1;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s_fpre[mid] <= i) lo = mid; else hi = mid;
+  }
+  return fin[(size_t)lo * a.fcap + (i - s_fpre[lo])];
+}
+
 // ------------------------------------------------------------ parent kernel
+// Pass 1 decides each parent (threshold), aggregates the launching ones and
+// writes their records (block barriers); pass 2 runs the thresholded parents'
+// serial children with no barrier, so waves do not wait on each other.
 template <int P, int G>
 __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
@@ -289,131 +349,133 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   }
 
   Stage s{s_stage[wave], 0u};
-  uint32_t sv[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+  Counters cn{0, 0, 0, 0, 0, 0, 0};
   const uint32_t nvb = ceil_div(F, PB);
+
+  // ---- pass 1: threshold, coarsened grid size, aggregation, launch records
+  if (G != AGG_FLAT) {
+    for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+      const uint32_t i = vb * PB + tid;
+      int32_t start = 0, deg = 0;
+      uint32_t du = 0;
+      if (i < F) {
+        const int32_t u = frontier_at(a, fin, s_fpre, i);
+        start = a.rp[u];
+        deg = a.rp[u + 1] - start;
+        if (P == PROB_SSSP && deg >= a.T) du = a.dist[u];
+      }
+      const bool launch = deg > 0 && deg >= a.T;
+      // coarsened grid size (Sec. IV-B)
+      const uint32_t gdim = launch ? ceil_div((uint32_t)deg, (uint32_t)a.CB) : 0u;
+      const uint32_t cg = ceil_div(gdim, (uint32_t)a.CF);
+      if (launch) ++cn.rec;
+
+      if (G == AGG_NONE) {
+        // every launching parent publishes its own grid; its record sits at
+        // its frontier index
+        if (launch) {
+          a.rec[i] = make_int4(start, deg, 0, (int32_t)du);
+          publish(a, cur, vb % NQD, i, 1u, cg);
+          ++cn.desc;
+        }
+      } else if (G == AGG_WAVE) {
+        const unsigned long long m = __ballot(launch);
+        if (m) {  // wave-uniform
+          const uint32_t incl = wave_incl_scan(cg, lane);
+          const uint32_t total = __shfl(incl, 63, 64);
+          const uint32_t seg = vb * PB + wave * 64;
+          if (launch)
+            a.rec[seg + lane_rank(m)] = make_int4(start, deg, (int32_t)(incl - cg), (int32_t)du);
+          if (lane == 0) {
+            publish(a, cur, vb % NQD, seg, (uint32_t)__popcll(m), total);
+            ++cn.desc;
+          }
+        }
+      } else {
+        // block-level scan of (launch, cg): wave scans, then across waves in LDS
+        const unsigned long long m = __ballot(launch);
+        const uint32_t incl = wave_incl_scan(cg, lane);
+        if (lane == 63) {
+          s_scan[wave] = (uint32_t)__popcll(m);
+          s_scan[NW + wave] = incl;
+        }
+        __syncthreads();
+        uint32_t roff = 0, coff = 0, nrec_b = 0, total_b = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          if (w < wave) { roff += s_scan[w]; coff += s_scan[NW + w]; }
+          nrec_b += s_scan[w];
+          total_b += s_scan[NW + w];
+        }
+        if (G == AGG_BLOCK) {
+          const uint32_t seg = vb * PB;
+          if (launch)
+            a.rec[seg + roff + lane_rank(m)] =
+                make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
+          if (tid == 0 && nrec_b) {
+            publish(a, cur, vb % NQD, seg, nrec_b, total_b);
+            ++cn.desc;
+          }
+          __syncthreads();  // s_scan reuse
+        } else {  // AGG_MULTI: group of k consecutive virtual blocks (Sec. V-A)
+          const uint32_t g = vb / (uint32_t)a.k;
+          const uint32_t seg = g * (uint32_t)a.k * PB;
+          unsigned long long* gp = &a.grp_packed[(L % 3) * a.ngroups_cap + g];
+          uint32_t* gd = &a.grp_done[(L % 3) * a.ngroups_cap + g];
+          if (tid == 0) {
+            unsigned long long old = 0;
+            if (nrec_b)
+              old = atomicAdd(gp, ((unsigned long long)nrec_b << 32) | (unsigned long long)total_b);
+            s_bc[0] = (uint32_t)(old >> 32);
+            s_bc[1] = (uint32_t)old;
+          }
+          __syncthreads();
+          const uint32_t slot0 = s_bc[0], off0 = s_bc[1];
+          if (launch)
+            a.rec[seg + slot0 + roff + lane_rank(m)] =
+                make_int4(start, deg, (int32_t)(off0 + coff + incl - cg), (int32_t)du);
+          if (tid == 0) {
+            // the group's last block to finish "launches" the aggregated grid;
+            // its packed-counter add returned before this increment was issued
+            const uint32_t in_group = min((uint32_t)a.k, nvb - g * (uint32_t)a.k);
+            const uint32_t done = atomicAdd(gd, 1u);
+            if (done == in_group - 1) {
+              const unsigned long long tot = atomicAdd(gp, 0ull);
+              const uint32_t nrec_g = (uint32_t)(tot >> 32);
+              if (nrec_g) {
+                publish(a, cur, g % NQD, seg, nrec_g, (uint32_t)tot);
+                ++cn.desc;
+              }
+            }
+          }
+          __syncthreads();  // s_scan / s_bc reuse
+        }
+      }
+    }
+  }
+
+  // ---- pass 2: thresholded children run serially in their parent (Sec. III-B)
   for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     const uint32_t i = vb * PB + tid;
     int32_t start = 0, deg = 0;
     uint32_t du = 0;
     if (i < F) {
-      uint32_t lo = 0, hi = NQF + 1;  // queue of entry i: s_fpre[q] <= i < s_fpre[q + 1]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_fpre[mid] <= i) lo = mid; else hi = mid;
-      }
-      const int32_t u = fin[(size_t)lo * a.fcap + (i - s_fpre[lo])];
+      const int32_t u = frontier_at(a, fin, s_fpre, i);
       start = a.rp[u];
       deg = a.rp[u + 1] - start;
-      if (P == PROB_SSSP) du = a.dist[u];
-      ++sv[S_FRONT];
+      ++cn.front;
+      const bool ser = deg > 0 && (G == AGG_FLAT || deg < a.T);
+      if (!ser) deg = 0;
+      if (P == PROB_SSSP && ser) du = a.dist[u];
+      if (ser) { ++cn.serial; cn.eser += deg; }
     }
-    if (G == AGG_FLAT) {
-      if (deg > 0) { ++sv[S_SERIAL]; sv[S_ESER] += deg; }
-      serial_children<P>(a, start, deg, du, L, s, cur, fout, lane);
-      continue;
-    }
-    const bool launch = deg > 0 && deg >= a.T;
-    const bool ser = deg > 0 && !launch;
-    if (ser) { ++sv[S_SERIAL]; sv[S_ESER] += deg; }
-    // thresholded children run in the parent (Sec. III-B)
-    serial_children<P>(a, start, ser ? deg : 0, du, L, s, cur, fout, lane);
-    // coarsened grid size (Sec. IV-B)
-    const uint32_t gdim = launch ? ceil_div((uint32_t)deg, (uint32_t)a.CB) : 0u;
-    const uint32_t cg = ceil_div(gdim, (uint32_t)a.CF);
-    if (launch) ++sv[S_REC];
-
-    if (G == AGG_NONE) {
-      // every launching parent publishes its own grid; its record sits at its
-      // frontier index
-      if (launch) {
-        a.rec[i] = make_int4(start, deg, 0, (int32_t)du);
-        publish(a, cur, vb % NQD, i, 1u, cg);
-        ++sv[S_DESC];
-      }
-    } else if (G == AGG_WAVE) {
-      const unsigned long long m = __ballot(launch);
-      if (m) {  // wave-uniform
-        const uint32_t incl = wave_incl_scan(cg, lane);
-        const uint32_t total = __shfl(incl, 63, 64);
-        const uint32_t seg = vb * PB + wave * 64;
-        if (launch)
-          a.rec[seg + lane_rank(m)] = make_int4(start, deg, (int32_t)(incl - cg), (int32_t)du);
-        if (lane == 0) {
-          publish(a, cur, vb % NQD, seg, (uint32_t)__popcll(m), total);
-          ++sv[S_DESC];
-        }
-      }
-    } else {
-      // block-level scan of (launch, cg): wave scans, then across waves in LDS
-      const unsigned long long m = __ballot(launch);
-      const uint32_t incl = wave_incl_scan(cg, lane);
-      if (lane == 63) {
-        s_scan[wave] = (uint32_t)__popcll(m);
-        s_scan[NW + wave] = incl;
-      }
-      __syncthreads();
-      uint32_t roff = 0, coff = 0, nrec_b = 0, total_b = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        if (w < wave) { roff += s_scan[w]; coff += s_scan[NW + w]; }
-        nrec_b += s_scan[w];
-        total_b += s_scan[NW + w];
-      }
-      if (G == AGG_BLOCK) {
-        const uint32_t seg = vb * PB;
-        if (launch)
-          a.rec[seg + roff + lane_rank(m)] =
-              make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
-        if (tid == 0 && nrec_b) {
-          publish(a, cur, vb % NQD, seg, nrec_b, total_b);
-          ++sv[S_DESC];
-        }
-        __syncthreads();  // s_scan reuse
-      } else {  // AGG_MULTI: group of k consecutive virtual blocks (Sec. V-A)
-        const uint32_t g = vb / (uint32_t)a.k;
-        const uint32_t seg = g * (uint32_t)a.k * PB;
-        unsigned long long* gp = &a.grp_packed[(L % 3) * a.ngroups_cap + g];
-        uint32_t* gd = &a.grp_done[(L % 3) * a.ngroups_cap + g];
-        if (tid == 0) {
-          unsigned long long old = 0;
-          if (nrec_b)
-            old = atomicAdd(gp, ((unsigned long long)nrec_b << 32) | (unsigned long long)total_b);
-          s_bc[0] = (uint32_t)(old >> 32);
-          s_bc[1] = (uint32_t)old;
-        }
-        __syncthreads();
-        const uint32_t slot0 = s_bc[0], off0 = s_bc[1];
-        if (launch)
-          a.rec[seg + slot0 + roff + lane_rank(m)] =
-              make_int4(start, deg, (int32_t)(off0 + coff + incl - cg), (int32_t)du);
-        if (tid == 0) {
-          // the group's last block to finish "launches" the aggregated grid;
-          // its packed-counter add returned before this increment was issued
-          const uint32_t in_group = min((uint32_t)a.k, nvb - g * (uint32_t)a.k);
-          const uint32_t done = atomicAdd(gd, 1u);
-          if (done == in_group - 1) {
-            const unsigned long long tot = atomicAdd(gp, 0ull);
-            const uint32_t nrec_g = (uint32_t)(tot >> 32);
-            if (nrec_g) {
-              publish(a, cur, g % NQD, seg, nrec_g, (uint32_t)tot);
-              ++sv[S_DESC];
-            }
-          }
-        }
-        __syncthreads();  // s_scan / s_bc reuse
-      }
-    }
+    serial_children<P>(a, start, deg, du, L, s, cur, fout, lane);
   }
   block_flush(s, a, cur, fout, tid, s_bc);
-  add_stats(a, s_stats, sv, tid);
+  add_stats(a, s_stats, cn, tid);
 }
 
 // ------------------------------------------------------------ child kernel
-struct Cursor {
-  uint32_t q, d, r, j;   // queue, descriptor, record within descriptor, block within record
-  uint32_t rec_base, nrec;
-};
-
 // Largest p in [0, n) with key(p) <= t, where key(0) <= t and keys increase:
 // 64-ary wave search (each round narrows the range 64-fold).
 template <typename KeyFn>
@@ -430,10 +492,16 @@ __device__ __forceinline__ uint32_t wave_upper_search(uint32_t n, uint32_t t, in
   return lo;
 }
 
+// One wave runs one coarsened child block at a time: the wave's share of the
+// aggregated blocks is contiguous, so the first block is disaggregated by
+// search and the following ones by advancing along the scanned offsets, with
+// the next record fetched while the current block runs.
 template <int P, int CF>
 __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_bc[NW + 8];
+  __shared__ uint32_t s_qpre[NQD + 1];
+  __shared__ uint32_t s_qnd[NQD];
   __shared__ unsigned long long s_stats[NSTAT];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -444,97 +512,131 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   int32_t* fout = (L & 1) ? a.front0 : a.front1;
 
   // aggregated child blocks of this level, queue by queue
-  uint32_t qpre[NQD + 1];
-  uint32_t qnd[NQD];
-  qpre[0] = 0;
-#pragma unroll
-  for (int q = 0; q < NQD; ++q) {
-    const unsigned long long c = cur->qctr[q];
-    qnd[q] = (uint32_t)(c >> 32);
-    qpre[q + 1] = qpre[q] + (uint32_t)c;
+  if (wave == 0) {
+    const unsigned long long c = lane < NQD ? cur->qctr[lane] : 0ull;
+    const uint32_t incl = wave_incl_scan((uint32_t)c, lane);
+    if (lane < NQD) {
+      s_qnd[lane] = (uint32_t)(c >> 32);
+      s_qpre[lane + 1] = incl;
+    }
+    if (lane == 0) s_qpre[0] = 0;
   }
-  const uint32_t B = qpre[NQD];
-  if (B == 0) return;
-  const uint32_t t0 = (uint32_t)((uint64_t)blockIdx.x * B / gridDim.x);
-  const uint32_t t1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * B / gridDim.x);
   if (tid < NSTAT) s_stats[tid] = 0;
   __syncthreads();
-  uint32_t sv[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const uint32_t B = s_qpre[NQD];
+  if (B == 0) return;
+  const uint32_t nwaves = gridDim.x * NW, gw = blockIdx.x * NW + wave;
+  const uint32_t t0 = (uint32_t)((uint64_t)gw * B / nwaves);
+  const uint32_t t1 = (uint32_t)((uint64_t)(gw + 1) * B / nwaves);
+  Counters cn{0, 0, 0, 0, 0, 0, 0};
   Stage s{s_stage[wave], 0u};
+  const uint32_t CB = (uint32_t)a.CB;
 
   if (t0 < t1) {
     // disaggregation of the first block (Sec. V-A): queue, descriptor, record
-    Cursor c{0, 0, 0, 0, 0, 0};
-    while (t0 >= qpre[c.q + 1]) ++c.q;
-    const int4* dq = a.desc + (size_t)c.q * a.desc_cap;
-    const uint32_t tq = t0 - qpre[c.q];
-    c.d = wave_upper_search(qnd[c.q], tq, lane, [&](uint32_t p) { return (uint32_t)dq[p].z; });
-    int4 dd = dq[c.d];
-    c.rec_base = (uint32_t)dd.x;
-    c.nrec = (uint32_t)dd.y;
+    uint32_t q = 0;
+    while (t0 >= s_qpre[q + 1]) ++q;
+    const int4* dq = a.desc + (size_t)q * a.desc_cap;
+    const uint32_t tq = t0 - s_qpre[q];
+    uint32_t d = wave_upper_search(s_qnd[q], tq, lane, [&](uint32_t p) { return (uint32_t)dq[p].z; });
+    int4 dd = dq[d];
     const uint32_t tr = tq - (uint32_t)dd.z;
-    c.r = wave_upper_search(c.nrec, tr, lane,
-                            [&](uint32_t p) { return (uint32_t)a.rec[c.rec_base + p].z; });
-    int4 rc = a.rec[c.rec_base + c.r];
-    c.j = tr - (uint32_t)rc.z;
-    const int32_t CB = a.CB;
-    for (uint32_t t = t0;;) {
-      const int32_t start = rc.x, deg = rc.y;
-      const uint32_t cgr = ceil_div(ceil_div((uint32_t)deg, (uint32_t)CB), (uint32_t)CF);
-      if (deg <= 0 || start < 0 || (int64_t)start + deg > (int64_t)a.m || c.j >= cgr) {
-        if (tid == 0) set_error(st, ERR_CAPACITY);
+    uint32_t r = wave_upper_search((uint32_t)dd.y, tr, lane,
+                                   [&](uint32_t p) { return (uint32_t)a.rec[dd.x + p].z; });
+    uint32_t j = tr - (uint32_t)a.rec[dd.x + r].z;
+
+    // Record window: lane i holds record r0 + i of the current descriptor, so
+    // consecutive small records cost one wave-wide load.
+    uint32_t r0 = r, wn = min(64u, (uint32_t)dd.y - r0);
+    int4 win = (uint32_t)lane < wn ? a.rec[dd.x + r0 + lane] : make_int4(0, 0, 0, 0);
+    uint32_t slice = 0;  // next 64-lane slice of block j of record r
+    uint32_t t = t0;     // child block being sliced
+    constexpr int U = 8;
+    bool bad = false;
+    while (t < t1 && !bad) {
+      // Fill U slots with 64-lane slices of consecutive aggregated child blocks.
+      // Coarsening loop (Sec. IV-B): block j of a record covers original
+      // blocks j*CF .. j*CF+CF-1 of CB lanes, i.e. the contiguous edge range
+      // [j*CF*CB, (j+1)*CF*CB), taken here 64 lanes at a time.
+      int32_t e0[U], cnt[U];
+      uint32_t dus[U];
+      int filled = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        e0[u] = 0;
+        cnt[u] = 0;
+        dus[u] = 0;
+        if (t < t1 && !bad && r - r0 < wn) {
+          const uint32_t wi = r - r0;
+          const int32_t start = __builtin_amdgcn_readlane(win.x, wi);
+          const int32_t deg = __builtin_amdgcn_readlane(win.y, wi);
+          const uint32_t du = (uint32_t)__builtin_amdgcn_readlane(win.w, wi);
+          const uint32_t cgr = ceil_div(ceil_div((uint32_t)deg, (uint32_t)a.CB), (uint32_t)CF);
+          if (deg <= 0 || start < 0 || (int64_t)start + deg > (int64_t)a.m || j >= cgr) {
+            bad = true;
+          } else {
+            const int32_t base_idx = (int32_t)(j * CF * a.CB);
+            const int32_t blim = min(deg - base_idx, CF * a.CB);
+            const int32_t off = (int32_t)slice * 64;
+            e0[u] = start + base_idx + off;
+            cnt[u] = min(64, blim - off);
+            dus[u] = du;
+            filled = u + 1;
+            if (off + 64 >= blim) {  // block done
+              slice = 0;
+              ++t;
+              if (lane == 0) ++cn.child;
+              if (++j == cgr) {
+                j = 0;
+                ++r;
+              }
+            } else {
+              ++slice;
+            }
+          }
+        }
+      }
+      if (bad) {
+        if (lane == 0) set_error(st, ERR_CAPACITY);
         break;
       }
-      if (tid == 0) ++sv[S_CHILD];
-      // coarsening loop (Sec. IV-B): original blocks j*CF .. j*CF+CF-1 of CB
-      // lanes cover the contiguous edge range [j*CF*CB, (j+1)*CF*CB)
-      const int32_t base_idx = (int32_t)c.j * CF * CB;
-      const int32_t lim = min(deg - base_idx, CF * CB);
-      const int32_t e0 = start + base_idx;
-      int32_t v[CF];
-      uint32_t w[CF];
+      int32_t v[U];
+      uint32_t w[U];
+      bool f[U];
 #pragma unroll
-      for (int r = 0; r < CF; ++r) {
-        const int32_t x = tid + r * PB;
-        v[r] = (x < lim) ? a.col[e0 + x] : -1;
-        w[r] = (P == PROB_SSSP && x < lim) ? a.w[e0 + x] : 0u;
+      for (int u = 0; u < U; ++u) {
+        const bool on = lane < cnt[u];
+        v[u] = on ? a.col[e0[u] + lane] : -1;
+        w[u] = (P == PROB_SSSP && on) ? a.w[e0[u] + lane] : 0u;
+        if (on) ++cn.echild;
       }
+      visit_batch<P, U>(a, v, w, dus, L, f);
 #pragma unroll
-      for (int r = 0; r < CF; ++r) {
-        if (r * PB < lim) {  // uniform across the workgroup
-          bool f = false;
-          if (v[r] >= 0) {
-            ++sv[S_ECHILD];
-            f = visit<P>(a, v[r], w[r], (uint32_t)rc.w, L);
-          }
-          stage_push(s, f, v[r], a, cur, fout, lane);
-        }
-      }
-      if (++t >= t1) break;
-      // advance to the next aggregated child block
-      if (++c.j == cgr) {
-        c.j = 0;
-        if (++c.r == c.nrec) {
-          c.r = 0;
-          if (++c.d == qnd[c.q]) {
-            c.d = 0;
-            do { ++c.q; } while (c.q < NQD && qnd[c.q] == 0);
-            if (c.q >= NQD) {
-              if (tid == 0) set_error(st, ERR_CAPACITY);
+      for (int u = 0; u < U; ++u) stage_push(s, f[u], v[u], a, cur, fout, lane);
+      (void)filled;
+      // refill the record window when it is used up
+      if (t < t1 && r - r0 >= wn) {
+        if (r >= (uint32_t)dd.y) {  // next descriptor (next queue if need be)
+          r = 0;
+          if (++d >= s_qnd[q]) {
+            d = 0;
+            do { ++q; } while (q < NQD && s_qnd[q] == 0);
+            if (q >= NQD) {
+              if (lane == 0) set_error(st, ERR_CAPACITY);
               break;
             }
-            dq = a.desc + (size_t)c.q * a.desc_cap;
+            dq = a.desc + (size_t)q * a.desc_cap;
           }
-          dd = dq[c.d];
-          c.rec_base = (uint32_t)dd.x;
-          c.nrec = (uint32_t)dd.y;
+          dd = dq[d];
         }
-        rc = a.rec[c.rec_base + c.r];
+        r0 = r;
+        wn = min(64u, (uint32_t)dd.y - r0);
+        win = (uint32_t)lane < wn ? a.rec[dd.x + r0 + lane] : make_int4(0, 0, 0, 0);
       }
     }
   }
   block_flush(s, a, cur, fout, tid, s_bc);
-  add_stats(a, s_stats, sv, tid);
+  add_stats(a, s_stats, cn, tid);
 }
 
 // ------------------------------------------------------------ init / advance
