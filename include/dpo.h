@@ -13,8 +13,9 @@
  *     group of k blocks are fused into one grid whose blocks find their parent
  *     by a binary search of the scanned grid sizes.
  * HIP has no device-side grid launch, so a "launch" is a device-resident
- * launch record plus a published descriptor that the same persistent kernel
- * consumes once the parent work is claimed.
+ * launch record plus a published descriptor; the aggregated child grids of a
+ * level run in the child kernel that follows the level's parent kernel on the
+ * same stream.
  *
  * Conventions for every call below
  *   - Graph arrays, outputs and the workspace are DEVICE pointers owned by the
@@ -25,10 +26,10 @@
  *   - Work is enqueued on `stream`.  The traversal calls synchronise `stream`
  *     once per `steps_per_replay` level steps to read the done flag, so they
  *     return only when the traversal has finished and outputs are final.
- *   - Errors are return codes, never exceptions.  Argument errors are found on
+ * *   - Errors are return codes, never exceptions.  Argument errors are found on
  *     the host before anything is enqueued.  Device-detected errors (queue
- *     capacity, a wait that exceeded its spin limit) are read back at the end
- *     of the call.
+ *     capacity, a vertex id out of range) are read back at the end of the
+ *     call.
  *   - Not thread-safe for concurrent calls that share a workspace.
  */
 #ifndef DPO_H
@@ -47,7 +48,7 @@ typedef enum {
   DPO_ERR_SOURCE = -2,      /* source outside [0, n)                             */
   DPO_ERR_WORKSPACE = -3,   /* ws_bytes < dpo_workspace_bytes(...)               */
   DPO_ERR_CAPACITY = -4,    /* a device queue would have overflowed              */
-  DPO_ERR_TIMEOUT = -5,     /* a device wait hit its spin limit, or level cap    */
+  DPO_ERR_TIMEOUT = -5,     /* more level steps than the traversal can need      */
   DPO_ERR_HIP = -6,         /* a HIP runtime call failed                         */
   DPO_ERR_UNSUPPORTED = -7  /* option combination not built into the library    */
 } dpo_status;
@@ -108,10 +109,11 @@ void dpo_default_options(dpo_options* o);
 
 /* Device workspace bytes needed by dpo_bfs / dpo_sssp on a graph with g->n
  * vertices under options o (the same buffer serves both).  0 on bad args.
- * Layout, all inside the caller's buffer: traversal state and counters,
- * two frontier queues of n int32, a per-vertex visit word (bitmap for BFS,
- * iteration stamp for SSSP), n launch records of 16 bytes and the
- * descriptor queue (16 bytes per possible aggregated grid). */
+ * Layout, all inside the caller's buffer: traversal state and counters, two
+ * frontier buffers (64 sharded queues plus an overflow queue), a per-vertex
+ * visit word (bitmap for BFS, iteration stamp for SSSP), launch records of
+ * 20 bytes per vertex, 8 descriptor queues of 16 bytes per possible
+ * aggregated grid and per-workgroup counters. */
 size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o);
 
 /* Breadth-first search (Table I, BFS) from `source`.
@@ -129,6 +131,49 @@ dpo_status dpo_bfs(const dpo_csr* g, int32_t source, const dpo_options* o, int32
  * 0xFFFFFFFF if unreachable.  Other arguments as for dpo_bfs. */
 dpo_status dpo_sssp(const dpo_csr* g, int32_t source, const dpo_options* o, uint32_t* dist,
                     void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
+
+/* ------------------------------------------------------------------ batches
+ * Many traversals in one launch sequence (the parent and child kernels of a
+ * level serve every traversal of the batch; frontier entries carry their
+ * traversal).  Graphs are packed in one CSR arena: graph g owns the arena
+ * vertices [graph_vbase[g], graph_vbase[g + 1]), its rows list arena vertex
+ * ids, and no edge leaves a graph. */
+typedef struct {
+  int32_t ngraphs;             /* >= 1                                              */
+  const int32_t* graph_vbase;  /* HOST int32[ngraphs + 1], graph_vbase[0] = 0,
+                                  graph_vbase[ngraphs] = csr.n, strictly increasing  */
+  dpo_csr csr;                 /* the arena (device arrays, as for dpo_bfs)          */
+} dpo_arena;
+
+typedef struct {
+  int32_t graph;   /* graph index in the arena                                  */
+  int32_t source;  /* vertex id local to that graph                             */
+  int32_t bucket;  /* options entry whose threshold and coarsen this query uses */
+} dpo_query;
+
+/* Output layout of a batch: query i writes its graph's n_g results at
+ * [slot0[i], slot0[i] + n_g), slot0[i] = sum over j < i of round_up(n_g(j), 32).
+ * Returns the total number of slots (the output length) and, if slot0 is not
+ * NULL, fills the HOST array slot0[nq + 1].  -1 on bad arguments. */
+int64_t dpo_batch_slots(const dpo_arena* arena, const dpo_query* queries, int32_t nq,
+                        int64_t* slot0);
+
+/* Device workspace bytes for dpo_bfs_batch / dpo_sssp_batch (0 on bad args). */
+size_t dpo_batch_workspace_bytes(const dpo_arena* arena, const dpo_query* queries, int32_t nq,
+                                 const dpo_options* o);
+
+/* nq (<= 4096) traversals at once.  bucket_opts[b] supplies threshold and
+ * coarsen for the queries of bucket b (per-size-bucket tuning); mode, agg,
+ * agg_blocks, child_block and steps_per_replay come from bucket_opts[0].
+ * levels / dist: device arrays of dpo_batch_slots(...) entries, laid out as
+ * above; every query's results are bit-identical to a single dpo_bfs /
+ * dpo_sssp call on its graph.  Returns when all queries have finished. */
+dpo_status dpo_bfs_batch(const dpo_arena* arena, const dpo_query* queries, int32_t nq,
+                         const dpo_options* bucket_opts, int32_t nbuckets, int32_t* levels,
+                         void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
+dpo_status dpo_sssp_batch(const dpo_arena* arena, const dpo_query* queries, int32_t nq,
+                          const dpo_options* bucket_opts, int32_t nbuckets, uint32_t* dist,
+                          void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
 
 /* Static string for a dpo_status value. */
 const char* dpo_strerror(int32_t status);

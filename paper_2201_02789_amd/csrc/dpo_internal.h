@@ -5,13 +5,14 @@
 
 namespace dpo {
 
-constexpr int PB = 256;        // parent workgroup: 256 frontier entries per virtual block
-constexpr int NW = PB / 64;    // wave64s per workgroup
-constexpr int STAGE = 512;     // LDS slots per wave for next-frontier staging
-constexpr int NQD = 8;         // descriptor queues (one per XCD: queue = virtual block % 8)
-constexpr int NQF = 64;        // frontier queues (queue = workgroup % 64), plus one overflow
-constexpr int MAX_GRID = 4096; // persistent grid cap (rows of the per-workgroup counters)
+constexpr int PB = 256;          // parent workgroup: 256 frontier entries per virtual block
+constexpr int NW = PB / 64;      // wave64s per workgroup
+constexpr int STAGE = 512;       // LDS slots per wave for next-frontier staging
+constexpr int NQD = 8;           // descriptor queues (one per XCD: queue = virtual block % 8)
+constexpr int NQF = 64;          // frontier queues (queue = workgroup % 64), plus one overflow
+constexpr int MAX_GRID = 4096;   // persistent grid cap (rows of the per-workgroup counters)
 constexpr int NSTAT = 8;
+constexpr int MAX_QUERIES = 4096;  // per-query tables are staged in LDS
 
 enum { PROB_BFS = 0, PROB_SSSP = 1 };
 enum { AGG_NONE = 0, AGG_WAVE = 1, AGG_BLOCK = 2, AGG_MULTI = 3, AGG_FLAT = 4 };
@@ -31,9 +32,23 @@ struct State {
   uint32_t base;        // level index of step 0 of the current graph replay
   uint32_t done;        // set when a level starts with an empty frontier
   uint32_t error;       // first device error code, 0 = none
-  uint32_t levels_run;  // non-empty levels
+  uint32_t levels_run;  // index of the last non-empty level + 1
   uint32_t pad[60];
   LevelSet set[3];
+};
+
+// One traversal ("query") of a batch.  Its outputs occupy the slots
+// [slot0, slot0 + n) of the output arena; slot s is vertex s - slot0 + vbase of
+// the CSR arena.
+struct Query {
+  int32_t slot0;   // first output slot
+  int32_t n;       // vertices of its graph
+  int32_t vbase;   // global id of its graph's vertex 0 in the CSR arena
+  int32_t lstart;  // level index at which it started (its source is at level lstart)
+  int32_t T;       // threshold of its size bucket
+  int32_t CF;      // coarsening factor of its size bucket
+  int32_t last;    // last level index with frontier entries (written by the kernels)
+  int32_t src;     // source (local id)
 };
 
 // Kernel arguments (by value).  All pointers are device pointers.
@@ -41,32 +56,36 @@ struct Args {
   const int32_t* rp;
   const int32_t* col;
   const uint32_t* w;
-  int32_t* level;
-  uint32_t* dist;
+  int32_t* level;                  // [slots] BFS output
+  uint32_t* dist;                  // [slots] SSSP output
   State* st;
+  Query* q;                        // [nq]
   unsigned long long* grp_packed;  // [3][ngroups_cap]: hi32 records, lo32 child blocks
   uint32_t* grp_done;              // [3][ngroups_cap]: blocks of the group finished
-  int32_t* front0;                 // [NQF * fcap + n]
+  int32_t* front0;                 // [NQF * fcap + slots]
   int32_t* front1;
-  uint32_t* visit;                 // BFS bitmap words / SSSP stamps
-  int4* rec;                       // [n] launch records {row start, deg, offset, parent value}
+  uint32_t* visit;                 // BFS bitmap words / SSSP stamps, indexed by slot
+  int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
+  int32_t* rec_q;                  // [slots] query of each record
   int4* desc;                      // [NQD][desc_cap] {record base, records, block base, -}
   unsigned long long* stats;       // [MAX_GRID][NSTAT], one row per workgroup
-  int32_t n;
-  int32_t m;
-  int32_t T;
+  int32_t slots;                   // total output slots (sum of the queries' n)
+  int32_t m;                       // CSR arena entries
+  int32_t nq;
   int32_t CB;
-  int32_t CF;
   int32_t k;
   int32_t ngroups_cap;
   int32_t desc_cap;                // per descriptor queue
   int32_t fcap;                    // per frontier queue
   int32_t count_stats;
+  int32_t pad;
 };
 
 const void* parent_kernel_ptr(int problem, int gran);
-const void* child_kernel_ptr(int problem, int cf);
+const void* child_kernel_ptr(int problem);
 const void* init_kernel_ptr(int problem);
+const void* admit_kernel_ptr(int problem);
+const void* admit_sources_kernel_ptr();
 const void* advance_kernel_ptr();
 
 }  // namespace dpo

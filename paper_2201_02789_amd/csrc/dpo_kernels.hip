@@ -38,9 +38,16 @@
 // coarsened block runs the coarsening loop over CF original blocks of CB lanes
 // (Sec. IV-B) with coalesced col_idx reads.
 //
-// Child body: BFS claims v in a visited bitmap (n bits, L2-resident) and
-// writes level[v] = L + 1; SSSP relaxes dist[v] with atomicMin and queues v
-// once per iteration through an iteration stamp.  New frontier vertices are
+// Child body: BFS claims v in a visited bitmap (one bit per output slot,
+// L2-resident) and writes its level; SSSP relaxes dist with atomicMin and
+// queues v once per iteration through an iteration stamp.
+//
+// Queries: a launch may carry many traversals ("queries") over graphs packed
+// in one CSR arena.  Query q owns the output slots [slot0, slot0 + n) (slot0 a
+// multiple of 32, so bitmap words never straddle queries); frontier entries
+// are slots.  A single traversal is a batch of one.  Queries may start at
+// different level indices (continuous batching): a vertex found at level
+// index L + 1 gets level L + 1 - lstart.  New frontier vertices are
 // staged per wave in LDS and appended to one of 64 frontier queues with one
 // atomic per flush, so no counter sees more than a few dozen atomics a level.
 #include <hip/hip_runtime.h>
@@ -93,7 +100,7 @@ __device__ __forceinline__ Reserve reserve_slots(const Args& a, LevelSet* ls, ui
   if (r.inseg < cnt) {
     const uint32_t rest = cnt - r.inseg;
     r.obase = atomicAdd(&ls->fcnt[NQF], rest);
-    if ((uint64_t)r.obase + rest > (uint64_t)a.n) set_error(a.st, ERR_CAPACITY);
+    if ((uint64_t)r.obase + rest > (uint64_t)a.slots) set_error(a.st, ERR_CAPACITY);
   }
   return r;
 }
@@ -104,7 +111,7 @@ __device__ __forceinline__ void put_slot(const Args& a, int32_t* buf, const Rese
     buf[(size_t)r.q * a.fcap + r.pos + p] = v;
   } else {
     const uint32_t o = r.obase + (p - r.inseg);
-    if (o < (uint32_t)a.n) buf[(size_t)NQF * a.fcap + o] = v;
+    if (o < (uint32_t)a.slots) buf[(size_t)NQF * a.fcap + o] = v;
   }
 }
 
@@ -167,65 +174,76 @@ __device__ __forceinline__ void block_flush(Stage& s, const Args& a, LevelSet* l
 }
 
 // ------------------------------------------------------------ child body
-// The child body for U neighbours of one lane at a time: all probes are
-// issued before any atomic, so the U memory round trips overlap.  BFS claims v
-// in the visited bitmap and writes level[v] = L + 1; SSSP relaxes dist[v] with
-// atomicMin and queues v once per iteration through its stamp.
+// Per-element context: query bounds and where its outputs live.
+struct Elem {
+  int32_t vbase;  // graph vertex 0 in the CSR arena
+  int32_t n;      // graph vertices
+  int32_t sbase;  // slot0 - vbase: slot of global vertex v is v + sbase
+  int32_t lv;     // level value written for a discovery (BFS)
+  uint32_t du;    // parent distance (SSSP)
+};
+
+// The child body for U neighbours at a time: all probes are issued before any
+// atomic, so the U memory round trips overlap.  BFS claims the slot in the
+// visited bitmap and writes its level; SSSP relaxes dist with atomicMin and
+// queues the slot once per iteration through its stamp.  out[u] = slot to
+// append, or -1.
 template <int P, int U>
 __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U],
-                                            const uint32_t (&w)[U], const uint32_t (&du)[U],
-                                            uint32_t L, bool (&f)[U]) {
-  bool ok[U];
+                                            const uint32_t (&w)[U], const Elem (&c)[U],
+                                            uint32_t L, int32_t (&out)[U]) {
+  int32_t sl[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    ok[u] = v[u] >= 0;
-    if (ok[u] && (uint32_t)v[u] >= (uint32_t)a.n) {
-      set_error(a.st, ERR_ARG);
-      ok[u] = false;
+    sl[u] = -1;
+    if (v[u] >= 0) {
+      const int32_t loc = v[u] - c[u].vbase;
+      if ((uint32_t)loc >= (uint32_t)c[u].n) set_error(a.st, ERR_ARG);
+      else sl[u] = v[u] + c[u].sbase;
     }
-    f[u] = false;
+    out[u] = -1;
   }
   if (P == PROB_BFS) {
     uint32_t word[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) word[u] = ok[u] ? a.visit[(uint32_t)v[u] >> 5] : ~0u;
+    for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? a.visit[(uint32_t)sl[u] >> 5] : ~0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t bit = 1u << (v[u] & 31);
-      if (ok[u] && !(word[u] & bit)) word[u] = atomicOr(&a.visit[(uint32_t)v[u] >> 5], bit);
+      const uint32_t bit = 1u << (sl[u] & 31);
+      if (sl[u] >= 0 && !(word[u] & bit)) word[u] = atomicOr(&a.visit[(uint32_t)sl[u] >> 5], bit);
       else word[u] = ~0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      f[u] = !(word[u] & (1u << (v[u] & 31)));
-      if (f[u]) a.level[v[u]] = (int32_t)(L + 1);
+      if (!(word[u] & (1u << (sl[u] & 31)))) {
+        a.level[sl[u]] = c[u].lv;
+        out[u] = sl[u];
+      }
     }
   } else {
     uint32_t nd[U], cur[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      nd[u] = du[u] + w[u];
-      cur[u] = ok[u] ? a.dist[v[u]] : 0u;
+      nd[u] = c[u].du + w[u];
+      cur[u] = sl[u] >= 0 ? a.dist[sl[u]] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (ok[u] && nd[u] < cur[u]) cur[u] = atomicMin(&a.dist[v[u]], nd[u]);
+      if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = atomicMin(&a.dist[sl[u]], nd[u]);
       else cur[u] = 0u;
     }
     const uint32_t it = L + 1;
     uint32_t stamp[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      f[u] = nd[u] < cur[u];  // improved
-      stamp[u] = f[u] ? a.visit[v[u]] : it;
-    }
+    for (int u = 0; u < U; ++u) stamp[u] = nd[u] < cur[u] ? a.visit[sl[u]] : it;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (f[u] && stamp[u] != it) stamp[u] = atomicExch(&a.visit[v[u]], it);
+      if (nd[u] < cur[u] && stamp[u] != it) stamp[u] = atomicExch(&a.visit[sl[u]], it);
       else stamp[u] = it;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) f[u] = stamp[u] != it;
+    for (int u = 0; u < U; ++u)
+      if (stamp[u] != it) out[u] = sl[u];
   }
 }
 
@@ -234,24 +252,24 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
 // neighbours in flight per lane.
 template <int P>
 __device__ __forceinline__ void serial_children(const Args& a, int32_t start, int32_t cnt,
-                                                uint32_t du, uint32_t L, Stage& s, LevelSet* ls,
-                                                int32_t* fout, int lane) {
+                                                const Elem& ctx, uint32_t L, Stage& s,
+                                                LevelSet* ls, int32_t* fout, int lane) {
   constexpr int U = 8;
   int32_t e = start;
   const int32_t end = start + cnt;
   while (__any(e < end)) {
-    int32_t v[U];
-    uint32_t w[U], dus[U];
-    bool f[U];
+    int32_t v[U], out[U];
+    uint32_t w[U];
+    Elem c[U];
 #pragma unroll
     for (int r = 0; r < U; ++r) {
       v[r] = (e + r < end) ? a.col[e + r] : -1;
       w[r] = (P == PROB_SSSP && e + r < end) ? a.w[e + r] : 0u;
-      dus[r] = du;
+      c[r] = ctx;
     }
-    visit_batch<P, U>(a, v, w, dus, L, f);
+    visit_batch<P, U>(a, v, w, c, L, out);
 #pragma unroll
-    for (int r = 0; r < U; ++r) stage_push(s, f[r], v[r], a, ls, fout, lane);
+    for (int r = 0; r < U; ++r) stage_push(s, out[r] >= 0, out[r], a, ls, fout, lane);
     e += U;
   }
 }
@@ -261,7 +279,8 @@ struct Counters {
 };
 
 // Per-workgroup counters: one row per workgroup, summed on the host.
-__device__ __forceinline__ void add_stats(const Args& a, unsigned long long* s_stats, const Counters& c, int tid) {
+__device__ __forceinline__ void add_stats(const Args& a, unsigned long long* s_stats,
+                                          const Counters& c, int tid) {
   if (!a.count_stats) return;
   if (c.front) atomicAdd(&s_stats[S_FRONT], (unsigned long long)c.front);
   if (c.serial) atomicAdd(&s_stats[S_SERIAL], (unsigned long long)c.serial);
@@ -298,10 +317,49 @@ __device__ __forceinline__ int32_t frontier_at(const Args& a, const int32_t* fin
   return fin[(size_t)lo * a.fcap + (i - s_fpre[lo])];
 }
 
+// Query owning slot s: largest q with slot0[q] <= s (table in LDS).
+__device__ __forceinline__ uint32_t query_of(const int32_t* s_q0, int32_t nq, int32_t s) {
+  uint32_t lo = 0, hi = (uint32_t)nq;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s_q0[mid] <= s) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// One parent thread: its query, vertex, row and parameters.
+struct Parent {
+  int32_t start, deg, T, CF, slot;
+  uint32_t q;
+  Elem e;
+};
+
+template <int P>
+__device__ __forceinline__ Parent load_parent(const Args& a, const int32_t* fin,
+                                              const uint32_t* s_fpre, const int32_t* s_q0,
+                                              uint32_t i, uint32_t L) {
+  Parent p;
+  p.slot = frontier_at(a, fin, s_fpre, i);
+  p.q = query_of(s_q0, a.nq, p.slot);
+  const Query Q = a.q[p.q];
+  const int32_t vg = Q.vbase + (p.slot - Q.slot0);
+  p.start = a.rp[vg];
+  p.deg = a.rp[vg + 1] - p.start;
+  p.T = Q.T;
+  p.CF = Q.CF;
+  p.e.vbase = Q.vbase;
+  p.e.n = Q.n;
+  p.e.sbase = Q.slot0 - Q.vbase;
+  p.e.lv = (int32_t)(L + 1) - Q.lstart;
+  p.e.du = 0;
+  return p;
+}
+
 // ------------------------------------------------------------ parent kernel
 // Pass 1 decides each parent (threshold), aggregates the launching ones and
 // writes their records (block barriers); pass 2 runs the thresholded parents'
 // serial children with no barrier, so waves do not wait on each other.
+// Dynamic LDS: the queries' first slots [nq] and one live bit per query.
 template <int P, int G>
 __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
@@ -309,6 +367,9 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ uint32_t s_scan[2 * NW];
   __shared__ uint32_t s_bc[NW + 8];
   __shared__ unsigned long long s_stats[NSTAT];
+  extern __shared__ int32_t s_dyn[];
+  int32_t* s_q0 = s_dyn;
+  uint32_t* s_live = (uint32_t*)(s_dyn + a.nq);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
@@ -328,6 +389,8 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     if (lane == 63) s_fpre[NQF + 1] = incl + prv->fcnt[NQF];
   }
   if (tid < NSTAT) s_stats[tid] = 0;
+  for (int i = tid; i < a.nq; i += PB) s_q0[i] = a.q[i].slot0;
+  for (int i = tid; i < (a.nq + 31) / 32; i += PB) s_live[i] = 0;
   __syncthreads();
   const uint32_t F = s_fpre[NQF + 1];
   if (F == 0) {
@@ -356,18 +419,21 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   if (G != AGG_FLAT) {
     for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
       const uint32_t i = vb * PB + tid;
-      int32_t start = 0, deg = 0;
-      uint32_t du = 0;
+      int32_t start = 0, deg = 0, q = 0;
+      uint32_t du = 0, cg = 0;
+      bool launch = false;
       if (i < F) {
-        const int32_t u = frontier_at(a, fin, s_fpre, i);
-        start = a.rp[u];
-        deg = a.rp[u + 1] - start;
-        if (P == PROB_SSSP && deg >= a.T) du = a.dist[u];
+        const Parent p = load_parent<P>(a, fin, s_fpre, s_q0, i, L);
+        start = p.start;
+        deg = p.deg;
+        q = (int32_t)p.q;
+        launch = deg > 0 && deg >= p.T;
+        if (launch) {
+          if (P == PROB_SSSP) du = a.dist[p.slot];
+          // coarsened grid size (Sec. IV-B)
+          cg = ceil_div(ceil_div((uint32_t)deg, (uint32_t)a.CB), (uint32_t)p.CF);
+        }
       }
-      const bool launch = deg > 0 && deg >= a.T;
-      // coarsened grid size (Sec. IV-B)
-      const uint32_t gdim = launch ? ceil_div((uint32_t)deg, (uint32_t)a.CB) : 0u;
-      const uint32_t cg = ceil_div(gdim, (uint32_t)a.CF);
       if (launch) ++cn.rec;
 
       if (G == AGG_NONE) {
@@ -375,6 +441,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         // its frontier index
         if (launch) {
           a.rec[i] = make_int4(start, deg, 0, (int32_t)du);
+          a.rec_q[i] = q;
           publish(a, cur, vb % NQD, i, 1u, cg);
           ++cn.desc;
         }
@@ -384,8 +451,10 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           const uint32_t incl = wave_incl_scan(cg, lane);
           const uint32_t total = __shfl(incl, 63, 64);
           const uint32_t seg = vb * PB + wave * 64;
-          if (launch)
+          if (launch) {
             a.rec[seg + lane_rank(m)] = make_int4(start, deg, (int32_t)(incl - cg), (int32_t)du);
+            a.rec_q[seg + lane_rank(m)] = q;
+          }
           if (lane == 0) {
             publish(a, cur, vb % NQD, seg, (uint32_t)__popcll(m), total);
             ++cn.desc;
@@ -409,9 +478,11 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         }
         if (G == AGG_BLOCK) {
           const uint32_t seg = vb * PB;
-          if (launch)
+          if (launch) {
             a.rec[seg + roff + lane_rank(m)] =
                 make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
+            a.rec_q[seg + roff + lane_rank(m)] = q;
+          }
           if (tid == 0 && nrec_b) {
             publish(a, cur, vb % NQD, seg, nrec_b, total_b);
             ++cn.desc;
@@ -431,9 +502,11 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           }
           __syncthreads();
           const uint32_t slot0 = s_bc[0], off0 = s_bc[1];
-          if (launch)
+          if (launch) {
             a.rec[seg + slot0 + roff + lane_rank(m)] =
                 make_int4(start, deg, (int32_t)(off0 + coff + incl - cg), (int32_t)du);
+            a.rec_q[seg + slot0 + roff + lane_rank(m)] = q;
+          }
           if (tid == 0) {
             // the group's last block to finish "launches" the aggregated grid;
             // its packed-counter add returned before this increment was issued
@@ -458,20 +531,26 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     const uint32_t i = vb * PB + tid;
     int32_t start = 0, deg = 0;
-    uint32_t du = 0;
+    Elem e{0, 0, 0, 0, 0u};
     if (i < F) {
-      const int32_t u = frontier_at(a, fin, s_fpre, i);
-      start = a.rp[u];
-      deg = a.rp[u + 1] - start;
+      Parent p = load_parent<P>(a, fin, s_fpre, s_q0, i, L);
+      start = p.start;
+      deg = p.deg;
+      e = p.e;
       ++cn.front;
-      const bool ser = deg > 0 && (G == AGG_FLAT || deg < a.T);
+      atomicOr(&s_live[p.q >> 5], 1u << (p.q & 31));
+      const bool ser = deg > 0 && (G == AGG_FLAT || deg < p.T);
       if (!ser) deg = 0;
-      if (P == PROB_SSSP && ser) du = a.dist[u];
+      if (P == PROB_SSSP && ser) e.du = a.dist[p.slot];
       if (ser) { ++cn.serial; cn.eser += deg; }
     }
-    serial_children<P>(a, start, deg, du, L, s, cur, fout, lane);
+    serial_children<P>(a, start, deg, e, L, s, cur, fout, lane);
   }
   block_flush(s, a, cur, fout, tid, s_bc);
+  // queries with frontier entries at this level are still running
+  __syncthreads();
+  for (int i = tid; i < a.nq; i += PB)
+    if (s_live[i >> 5] & (1u << (i & 31))) a.q[i].last = (int32_t)L;
   add_stats(a, s_stats, cn, tid);
 }
 
@@ -492,11 +571,37 @@ __device__ __forceinline__ uint32_t wave_upper_search(uint32_t n, uint32_t t, in
   return lo;
 }
 
+// Lane i of a wave holds record r0 + i of the current descriptor and the
+// fields of its query, so consecutive small records cost one wave-wide load.
+struct Window {
+  int4 rec;      // {row start, deg, offset, parent distance}
+  int32_t CF, vbase, n, sbase, lv;
+};
+
+__device__ __forceinline__ Window load_window(const Args& a, uint32_t base, uint32_t wn, int lane,
+                                              uint32_t L) {
+  Window w{make_int4(0, 0, 0, 0), 1, 0, 0, 0, 0};
+  if ((uint32_t)lane < wn) {
+    w.rec = a.rec[base + lane];
+    const int32_t q = a.rec_q[base + lane];
+    if ((uint32_t)q < (uint32_t)a.nq) {
+      const Query Q = a.q[q];
+      w.CF = Q.CF;
+      w.vbase = Q.vbase;
+      w.n = Q.n;
+      w.sbase = Q.slot0 - Q.vbase;
+      w.lv = (int32_t)(L + 1) - Q.lstart;
+    } else {
+      w.rec.y = 0;  // flagged below as a bad record
+    }
+  }
+  return w;
+}
+
 // One wave runs one coarsened child block at a time: the wave's share of the
 // aggregated blocks is contiguous, so the first block is disaggregated by
-// search and the following ones by advancing along the scanned offsets, with
-// the next record fetched while the current block runs.
-template <int P, int CF>
+// search and the following ones by advancing along the scanned offsets.
+template <int P>
 __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_bc[NW + 8];
@@ -545,10 +650,8 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
                                    [&](uint32_t p) { return (uint32_t)a.rec[dd.x + p].z; });
     uint32_t j = tr - (uint32_t)a.rec[dd.x + r].z;
 
-    // Record window: lane i holds record r0 + i of the current descriptor, so
-    // consecutive small records cost one wave-wide load.
     uint32_t r0 = r, wn = min(64u, (uint32_t)dd.y - r0);
-    int4 win = (uint32_t)lane < wn ? a.rec[dd.x + r0 + lane] : make_int4(0, 0, 0, 0);
+    Window win = load_window(a, (uint32_t)dd.x + r0, wn, lane, L);
     uint32_t slice = 0;  // next 64-lane slice of block j of record r
     uint32_t t = t0;     // child block being sliced
     constexpr int U = 8;
@@ -559,29 +662,31 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
       // blocks j*CF .. j*CF+CF-1 of CB lanes, i.e. the contiguous edge range
       // [j*CF*CB, (j+1)*CF*CB), taken here 64 lanes at a time.
       int32_t e0[U], cnt[U];
-      uint32_t dus[U];
-      int filled = 0;
+      Elem c[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         e0[u] = 0;
         cnt[u] = 0;
-        dus[u] = 0;
+        c[u] = Elem{0, 0, 0, 0, 0u};
         if (t < t1 && !bad && r - r0 < wn) {
           const uint32_t wi = r - r0;
-          const int32_t start = __builtin_amdgcn_readlane(win.x, wi);
-          const int32_t deg = __builtin_amdgcn_readlane(win.y, wi);
-          const uint32_t du = (uint32_t)__builtin_amdgcn_readlane(win.w, wi);
-          const uint32_t cgr = ceil_div(ceil_div((uint32_t)deg, (uint32_t)a.CB), (uint32_t)CF);
+          const int32_t start = __builtin_amdgcn_readlane(win.rec.x, wi);
+          const int32_t deg = __builtin_amdgcn_readlane(win.rec.y, wi);
+          const int32_t CF = __builtin_amdgcn_readlane(win.CF, wi);
+          const uint32_t cgr = ceil_div(ceil_div((uint32_t)deg, CB), (uint32_t)max(CF, 1));
           if (deg <= 0 || start < 0 || (int64_t)start + deg > (int64_t)a.m || j >= cgr) {
             bad = true;
           } else {
-            const int32_t base_idx = (int32_t)(j * CF * a.CB);
-            const int32_t blim = min(deg - base_idx, CF * a.CB);
+            const int32_t base_idx = (int32_t)(j * (uint32_t)CF * CB);
+            const int32_t blim = min(deg - base_idx, CF * (int32_t)CB);
             const int32_t off = (int32_t)slice * 64;
             e0[u] = start + base_idx + off;
             cnt[u] = min(64, blim - off);
-            dus[u] = du;
-            filled = u + 1;
+            c[u].vbase = __builtin_amdgcn_readlane(win.vbase, wi);
+            c[u].n = __builtin_amdgcn_readlane(win.n, wi);
+            c[u].sbase = __builtin_amdgcn_readlane(win.sbase, wi);
+            c[u].lv = __builtin_amdgcn_readlane(win.lv, wi);
+            c[u].du = (uint32_t)__builtin_amdgcn_readlane(win.rec.w, wi);
             if (off + 64 >= blim) {  // block done
               slice = 0;
               ++t;
@@ -600,9 +705,8 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
         if (lane == 0) set_error(st, ERR_CAPACITY);
         break;
       }
-      int32_t v[U];
+      int32_t v[U], out[U];
       uint32_t w[U];
-      bool f[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool on = lane < cnt[u];
@@ -610,10 +714,9 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
         w[u] = (P == PROB_SSSP && on) ? a.w[e0[u] + lane] : 0u;
         if (on) ++cn.echild;
       }
-      visit_batch<P, U>(a, v, w, dus, L, f);
+      visit_batch<P, U>(a, v, w, c, L, out);
 #pragma unroll
-      for (int u = 0; u < U; ++u) stage_push(s, f[u], v[u], a, cur, fout, lane);
-      (void)filled;
+      for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
       // refill the record window when it is used up
       if (t < t1 && r - r0 >= wn) {
         if (r >= (uint32_t)dd.y) {  // next descriptor (next queue if need be)
@@ -631,7 +734,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
         }
         r0 = r;
         wn = min(64u, (uint32_t)dd.y - r0);
-        win = (uint32_t)lane < wn ? a.rec[dd.x + r0 + lane] : make_int4(0, 0, 0, 0);
+        win = load_window(a, (uint32_t)dd.x + r0, wn, lane, L);
       }
     }
   }
@@ -639,38 +742,76 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   add_stats(a, s_stats, cn, tid);
 }
 
-// ------------------------------------------------------------ init / advance
-// Traversal start: outputs to "unreached", visit words and per-workgroup
-// counters cleared, level sets zeroed, the source alone in frontier 0.
-template <int P>
-__global__ __launch_bounds__(PB) void init_kernel(Args a, int32_t src) {
+// ------------------------------------------------------------ init / admit / advance
+// Traversal-set start: level sets and counters cleared.  Queries are
+// started by admit_kernel.
+__global__ __launch_bounds__(PB) void init_kernel(Args a) {
   const uint32_t gsz = gridDim.x * PB;
   const uint32_t gid = blockIdx.x * PB + threadIdx.x;
-  for (uint32_t v = gid; v < (uint32_t)a.n; v += gsz) {
-    if (P == PROB_BFS) {
-      a.level[v] = (v == (uint32_t)src) ? 0 : -1;
-    } else {
-      a.dist[v] = (v == (uint32_t)src) ? 0u : 0xFFFFFFFFu;
-      a.visit[v] = 0u;
-    }
-  }
-  if (P == PROB_BFS) {
-    const uint32_t words = ((uint32_t)a.n + 31) / 32;
-    for (uint32_t i = gid; i < words; i += gsz)
-      a.visit[i] = (i == (uint32_t)src >> 5) ? (1u << (src & 31)) : 0u;
-  }
   for (uint32_t i = gid; i < 3u * (uint32_t)a.ngroups_cap; i += gsz) {
     a.grp_packed[i] = 0;
     a.grp_done[i] = 0;
   }
   for (uint32_t i = gid; i < (uint32_t)(MAX_GRID * NSTAT); i += gsz) a.stats[i] = 0;
-  // frontier 0 = {src} in queue 0; its fill lives in the set of level -1 = set 2
-  const uint32_t src_fill =
-      (uint32_t)((__builtin_offsetof(State, set) + 2 * sizeof(LevelSet) +
-                  __builtin_offsetof(LevelSet, fcnt)) / 4);
   uint32_t* stw = (uint32_t*)a.st;
-  for (uint32_t i = gid; i < sizeof(State) / 4; i += gsz) stw[i] = (i == src_fill) ? 1u : 0u;
-  if (gid == 0) a.front0[0] = src;
+  for (uint32_t i = gid; i < sizeof(State) / 4; i += gsz) stw[i] = 0;
+}
+
+// Starts queries [q_first, q_first + q_count) at level index L = st->base:
+// their outputs set to "unreached" except the source, their visit words
+// cleared, their sources appended to the overflow queue of frontier L.
+// `reset` (host-known: the previous traversal set has finished) also clears
+// the level sets, whose fills are then stale.
+template <int P>
+__global__ __launch_bounds__(PB) void admit_kernel(Args a, int32_t q_first, int32_t q_count,
+                                                   int32_t reset) {
+  State* st = a.st;
+  const uint32_t L = st->base;
+  const uint32_t gsz = gridDim.x * PB;
+  const uint32_t gid = blockIdx.x * PB + threadIdx.x;
+  for (int32_t k = 0; k < q_count; ++k) {
+    const Query Q = a.q[q_first + k];
+    const uint32_t s0 = (uint32_t)Q.slot0, src = (uint32_t)Q.src;
+    for (uint32_t v = gid; v < (uint32_t)Q.n; v += gsz) {
+      if (P == PROB_BFS) {
+        a.level[s0 + v] = (v == src) ? 0 : -1;
+      } else {
+        a.dist[s0 + v] = (v == src) ? 0u : 0xFFFFFFFFu;
+        a.visit[s0 + v] = 0u;
+      }
+    }
+    if (P == PROB_BFS) {
+      const uint32_t words = ((uint32_t)Q.n + 31) / 32;
+      for (uint32_t i = gid; i < words; i += gsz)
+        a.visit[s0 / 32 + i] = (i == src >> 5) ? (1u << (src & 31)) : 0u;
+    }
+  }
+  if (reset) {
+    uint32_t* sw = (uint32_t*)&st->set[0];
+    for (uint32_t i = gid; i < 3 * sizeof(LevelSet) / 4; i += gsz) sw[i] = 0;
+    for (uint32_t i = gid; i < 3u * (uint32_t)a.ngroups_cap; i += gsz) {
+      a.grp_packed[i] = 0;
+      a.grp_done[i] = 0;
+    }
+  }
+}
+
+// Second half of admission (after admit_kernel): sources into frontier L.
+__global__ void admit_sources_kernel(Args a, int32_t q_first, int32_t q_count) {
+  State* st = a.st;
+  const uint32_t L = st->base;
+  LevelSet* ls = &st->set[(L + 2) % 3];  // fills of frontier L
+  int32_t* fin = (L & 1) ? a.front1 : a.front0;
+  const int32_t k = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k < q_count) {
+    Query* Q = &a.q[q_first + k];
+    Q->lstart = (int32_t)L;
+    Q->last = (int32_t)L;
+    const uint32_t pos = atomicAdd(&ls->fcnt[NQF], 1u);
+    if (pos < (uint32_t)a.slots) fin[(size_t)NQF * a.fcap + pos] = Q->slot0 + Q->src;
+    else set_error(st, ERR_CAPACITY);
+  }
+  if (k == 0) st->done = 0;
 }
 
 __global__ void advance_kernel(State* st, uint32_t steps) {
@@ -690,30 +831,23 @@ static const void* parent_for(int g) {
   }
 }
 
-template <int P>
-static const void* child_for(int cf) {
-  switch (cf) {
-    case 1: return (const void*)child_kernel<P, 1>;
-    case 2: return (const void*)child_kernel<P, 2>;
-    case 4: return (const void*)child_kernel<P, 4>;
-    case 8: return (const void*)child_kernel<P, 8>;
-    case 16: return (const void*)child_kernel<P, 16>;
-    default: return nullptr;
-  }
-}
-
 const void* parent_kernel_ptr(int problem, int gran) {
   return problem == PROB_BFS ? parent_for<PROB_BFS>(gran) : parent_for<PROB_SSSP>(gran);
 }
 
-const void* child_kernel_ptr(int problem, int cf) {
-  return problem == PROB_BFS ? child_for<PROB_BFS>(cf) : child_for<PROB_SSSP>(cf);
+const void* child_kernel_ptr(int problem) {
+  return problem == PROB_BFS ? (const void*)child_kernel<PROB_BFS>
+                             : (const void*)child_kernel<PROB_SSSP>;
 }
 
-const void* init_kernel_ptr(int problem) {
-  return problem == PROB_BFS ? (const void*)init_kernel<PROB_BFS>
-                             : (const void*)init_kernel<PROB_SSSP>;
+const void* init_kernel_ptr(int) { return (const void*)init_kernel; }
+
+const void* admit_kernel_ptr(int problem) {
+  return problem == PROB_BFS ? (const void*)admit_kernel<PROB_BFS>
+                             : (const void*)admit_kernel<PROB_SSSP>;
 }
+
+const void* admit_sources_kernel_ptr() { return (const void*)admit_sources_kernel; }
 
 const void* advance_kernel_ptr() { return (const void*)advance_kernel; }
 

@@ -53,6 +53,15 @@ class _Csr(ctypes.Structure):
                 ("col_idx", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
 
 
+class _Arena(ctypes.Structure):
+    _fields_ = [("ngraphs", ctypes.c_int32), ("graph_vbase", ctypes.POINTER(ctypes.c_int32)),
+                ("csr", _Csr)]
+
+
+class _Query(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("source", ctypes.c_int32), ("bucket", ctypes.c_int32)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("frontier_total", ctypes.c_int64), ("serial_parents", ctypes.c_int64),
@@ -116,6 +125,18 @@ def lib():
         f.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.POINTER(_Options),
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                       ctypes.POINTER(_Stats)]
+    L.dpo_batch_slots.restype = ctypes.c_int64
+    L.dpo_batch_slots.argtypes = [ctypes.POINTER(_Arena), ctypes.POINTER(_Query), ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_int64)]
+    L.dpo_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.dpo_batch_workspace_bytes.argtypes = [ctypes.POINTER(_Arena), ctypes.POINTER(_Query),
+                                            ctypes.c_int32, ctypes.POINTER(_Options)]
+    for name in ("dpo_bfs_batch", "dpo_sssp_batch"):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int32
+        f.argtypes = [ctypes.POINTER(_Arena), ctypes.POINTER(_Query), ctypes.c_int32,
+                      ctypes.POINTER(_Options), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(_Stats)]
     L.dpo_strerror.restype = ctypes.c_char_p
     L.dpo_strerror.argtypes = [ctypes.c_int32]
     _lib = L
@@ -221,6 +242,74 @@ def sssp(graph: DeviceGraph, source: int, opts: Options | None = None, stats: bo
     ws = alloc_workspace(graph, opts, graph.row_ptr.device)
     st = dpo_sssp(graph, source, opts, dist, ws, stats=stats)
     return dist, st
+
+
+class DeviceArena:
+    """Graphs packed in one CSR arena on the device (see graphgen.pack_arena)."""
+
+    def __init__(self, arena_graph, vbase, device="cuda"):
+        self.graph = DeviceGraph.from_host(arena_graph, device)
+        self.vbase = np.ascontiguousarray(vbase, dtype=np.int32)
+        self.ngraphs = int(self.vbase.size - 1)
+
+    def c(self) -> _Arena:
+        return _Arena(self.ngraphs, self.vbase.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                      self.graph.csr())
+
+
+def _queries(queries):
+    """[(graph, source[, bucket])] -> ctypes array of dpo_query."""
+    arr = (_Query * len(queries))()
+    for i, q in enumerate(queries):
+        arr[i] = _Query(int(q[0]), int(q[1]), int(q[2]) if len(q) > 2 else 0)
+    return arr
+
+
+def dpo_batch_slots(arena: DeviceArena, queries):
+    """(total slots, slot0 int64[nq + 1]) of the batch output layout."""
+    qa = _queries(queries)
+    slot0 = np.zeros(len(queries) + 1, dtype=np.int64)
+    tot = lib().dpo_batch_slots(ctypes.byref(arena.c()), qa, len(queries),
+                                slot0.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if tot < 0:
+        raise DpoError(DPO_ERR_ARG, "dpo_batch_slots")
+    return int(tot), slot0
+
+
+def dpo_batch_workspace_bytes(arena: DeviceArena, queries, opts: Options) -> int:
+    qa = _queries(queries)
+    return int(lib().dpo_batch_workspace_bytes(ctypes.byref(arena.c()), qa, len(queries),
+                                               ctypes.byref(opts.c())))
+
+
+def _batch(fn, what, arena, queries, bucket_opts, out, ws, stream, stats):
+    qa = _queries(queries)
+    ob = (_Options * len(bucket_opts))(*[o.c() for o in bucket_opts])
+    st = _Stats() if stats else None
+    rc = fn(ctypes.byref(arena.c()), qa, len(queries), ob, len(bucket_opts),
+            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_size_t(ws.numel() * ws.element_size()), _stream_ptr(stream),
+            ctypes.byref(st) if st is not None else None)
+    if rc != DPO_OK:
+        raise DpoError(rc, what)
+    if st is None:
+        return None
+    return {f: int(getattr(st, f)) for f, _ in _Stats._fields_ if f != "reserved"}
+
+
+def dpo_bfs_batch(arena: DeviceArena, queries, bucket_opts, levels, ws, stream=None,
+                  stats: bool = False):
+    """queries: [(graph, source[, bucket])]; bucket_opts: [Options] (threshold and
+    coarsen per bucket, the rest from bucket_opts[0]); levels: int32 device
+    tensor of dpo_batch_slots(...)[0] entries."""
+    return _batch(lib().dpo_bfs_batch, "dpo_bfs_batch", arena, queries, bucket_opts, levels, ws,
+                  stream, stats)
+
+
+def dpo_sssp_batch(arena: DeviceArena, queries, bucket_opts, dist, ws, stream=None,
+                   stats: bool = False):
+    return _batch(lib().dpo_sssp_batch, "dpo_sssp_batch", arena, queries, bucket_opts, dist, ws,
+                  stream, stats)
 
 
 def as_uint32(t) -> np.ndarray:

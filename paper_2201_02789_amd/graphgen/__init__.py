@@ -252,3 +252,45 @@ def relabel(g: Graph, perm: np.ndarray) -> Graph:
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr))
     e = np.stack([perm[src], perm[g.col_idx]], axis=1)
     return from_edges(n, e, g.weights, symmetric=False, name=g.name + "-relabel")
+
+
+def pack_arena(graphs):
+    """Packs graphs into one CSR arena: graph g's vertex v becomes arena vertex
+    vbase[g] + v.  Returns (arena Graph, vbase int32[len(graphs) + 1])."""
+    vbase = np.zeros(len(graphs) + 1, dtype=np.int64)
+    ebase = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        vbase[i + 1] = vbase[i] + g.n
+        ebase[i + 1] = ebase[i] + g.m
+    if vbase[-1] >= 2**31 or ebase[-1] >= 2**31:
+        raise ValueError("arena exceeds int32 indexing")
+    rp = np.empty(vbase[-1] + 1, dtype=np.int32)
+    col = np.empty(ebase[-1], dtype=np.int32)
+    weighted = all(g.weights is not None for g in graphs)
+    w = np.empty(ebase[-1], dtype=np.uint32) if weighted else None
+    for i, g in enumerate(graphs):
+        rp[vbase[i]:vbase[i + 1]] = g.row_ptr[:-1] + ebase[i]
+        col[ebase[i]:ebase[i + 1]] = g.col_idx + vbase[i]
+        if weighted:
+            w[ebase[i]:ebase[i + 1]] = g.weights
+    rp[-1] = ebase[-1]
+    return Graph(rp, col, w, "arena"), vbase.astype(np.int32)
+
+
+def batch_workload(seed: int = 40, ngraphs: int = 64, sources_per_graph: int = 8,
+                   scales=(10, 18), edgefactors=(8, 32)):
+    """The batched workload: ngraphs R-MAT graphs with scale ~ U{scales} and
+    edgefactor ~ U{edgefactors} drawn from `seed`, graph g generated with seed
+    1000 + g (permuted), sources_per_graph sources each from seed 2000 + g.
+    Returns (graphs, [(graph, source)])."""
+    rng = np.random.default_rng(seed)
+    sc = rng.integers(scales[0], scales[1] + 1, size=ngraphs)
+    ef = rng.integers(edgefactors[0], edgefactors[1] + 1, size=ngraphs)
+    graphs, queries = [], []
+    for g in range(ngraphs):
+        gr = rmat(int(sc[g]), int(ef[g]), 1000 + g, perm_seed=7000 + g,
+                  name=f"rmat-s{sc[g]}-ef{ef[g]}-seed{1000 + g}")
+        graphs.append(gr)
+        for s in sample_sources(gr, sources_per_graph, 2000 + g):
+            queries.append((g, int(s)))
+    return graphs, queries
