@@ -175,6 +175,50 @@ dpo_status dpo_sssp_batch(const dpo_arena* arena, const dpo_query* queries, int3
                           const dpo_options* bucket_opts, int32_t nbuckets, uint32_t* dist,
                           void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching over resident graphs.  Queries are submitted at any
+ * time; each dpo_engine_step() waits for the replay in flight (if any),
+ * retires the queries that finished (their results are copied to the
+ * caller's `out` before their tickets are reported), admits waiting queries
+ * in arrival order while a query-table entry and round_up(n_g, 32) free output
+ * slots are available (admission by footprint: a query that does not fit
+ * waits, and so do the ones behind it), and launches the next replay of
+ * steps_per_replay level steps without waiting for it.  Admitted queries join
+ * the running ones at the next level step; every result is bit-identical to a
+ * single dpo_bfs / dpo_sssp call.  One engine serves one kind (BFS or SSSP);
+ * engines on different streams overlap on the device. */
+typedef struct dpo_engine dpo_engine;
+
+/* Device workspace bytes for an engine (0 on bad args). */
+size_t dpo_engine_workspace_bytes(const dpo_options* o, int32_t max_queries, int64_t max_slots);
+
+/* kind: 0 = BFS, 1 = SSSP.  bucket_opts / nbuckets as for the batch calls;
+ * graph_bucket: HOST int32[arena->ngraphs] bucket of each graph (NULL = 0).
+ * max_queries <= 4096 running at once; max_slots: output slots shared by the
+ * running queries (the footprint pool).  ws: device, dpo_engine_workspace_bytes;
+ * out_arena: device int32/uint32[round_up(max_slots, 32)] engine-owned
+ * scratch for running queries' outputs.  The arena, ws and out_arena must
+ * outlive the engine.  The engine keeps a copy of graph_vbase. */
+dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_options* bucket_opts,
+                             int32_t nbuckets, const int32_t* graph_bucket, int32_t max_queries,
+                             int64_t max_slots, void* ws, size_t ws_bytes, void* out_arena,
+                             void* stream, dpo_engine** engine);
+
+/* Queue a query: `out` is a device array of n_g entries written before the
+ * ticket is reported by dpo_engine_poll.  DPO_ERR_CAPACITY if the graph can
+ * never fit in max_slots. */
+dpo_status dpo_engine_submit(dpo_engine* e, int32_t graph, int32_t source, void* out,
+                             uint64_t* ticket);
+
+/* One scheduling step (see above); running / pending: optional host outputs. */
+dpo_status dpo_engine_step(dpo_engine* e, int32_t* running, int32_t* pending);
+
+/* Moves up to cap completed tickets into tickets[]; returns how many. */
+int32_t dpo_engine_poll(dpo_engine* e, uint64_t* tickets, int32_t cap);
+
+/* Waits for the replay in flight and releases the engine's host resources. */
+void dpo_engine_destroy(dpo_engine* e);
+
 /* Static string for a dpo_status value. */
 const char* dpo_strerror(int32_t status);
 

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
+#include <map>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -25,7 +27,8 @@ constexpr int kMaxCachedGraphs = 64;
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t state, queries, grp_packed, grp_done, front0, front1, visit, rec, rec_q, desc, stats, total;
+  size_t state, queries, qlist, qmap, grp_packed, grp_done, front0, front1, visit, rec, rec_q, desc,
+      stats, total;
   int32_t ngroups_cap, desc_cap, fcap;
 };
 
@@ -64,6 +67,8 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   size_t off = 0;
   L.state = off; off = align_up(off + sizeof(State));
   L.queries = off; off = align_up(off + (size_t)nq * sizeof(Query));
+  L.qlist = off; off = align_up(off + (size_t)nq * 4);
+  L.qmap = off; off = align_up(off + (size_t)cdiv(slots, 32) * 4);
   L.grp_packed = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 8);
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
   L.front0 = off; off = align_up(off + fslots * 4);
@@ -118,6 +123,7 @@ struct Runtime {
   uint32_t* host_flags = nullptr;  // pinned: base, done, error, levels_run
   unsigned long long* host_stats = nullptr;  // pinned: MAX_GRID * NSTAT
   Query* host_q = nullptr;                   // pinned: MAX_QUERIES query records
+  int32_t* host_list = nullptr;              // pinned: MAX_QUERIES query indices
   int cu_count = 0;
   std::vector<GridEntry> grids;
 };
@@ -136,13 +142,14 @@ dpo_status ensure_runtime(Runtime& r) {
   if (hipDeviceGetAttribute(&r.cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return DPO_ERR_HIP;
   void* p = nullptr;
-  const size_t qbytes = (size_t)MAX_QUERIES * sizeof(Query);
+  const size_t qbytes = (size_t)MAX_QUERIES * (sizeof(Query) + 4);
   if (hipHostMalloc(&p, 256 + (size_t)MAX_GRID * NSTAT * 8 + qbytes, hipHostMallocDefault) !=
       hipSuccess)
     return DPO_ERR_HIP;
   r.host_flags = (uint32_t*)p;
   r.host_stats = (unsigned long long*)((char*)p + 256);
   r.host_q = (Query*)((char*)p + 256 + (size_t)MAX_GRID * NSTAT * 8);
+  r.host_list = (int32_t*)(r.host_q + MAX_QUERIES);
   return DPO_OK;
 }
 
@@ -178,14 +185,12 @@ dpo_status add_node(hipGraph_t graph, hipGraphNode_t* prev, const void* fn, int 
   return DPO_OK;
 }
 
-// Dynamic LDS of the parent kernel: the queries' first slots and live bits.
-unsigned parent_shmem(int32_t nq) { return (unsigned)(nq + (nq + 31) / 32) * 4u; }
-
 // K level steps (parent kernel, then child kernel unless flat) and the
 // advance of the level base, as one instantiated graph.
 dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid, int cgrid,
-                    int steps, const Args& args, hipGraphExec_t* out) {
+                    int steps, const Args& args, hipGraphExec_t* out, bool cached = true) {
   for (auto& e : r.graphs) {
+    if (!cached) break;
     if (e.parent == parent && e.child == child && e.pgrid == pgrid && e.cgrid == cgrid &&
         e.steps == steps && std::memcmp(&e.args, &args, sizeof(Args)) == 0) {
       e.last_use = ++r.tick;
@@ -202,7 +207,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid
   for (int i = 0; i < steps && s == DPO_OK; ++i) {
     step_ids[i] = (uint32_t)i;
     void* params[] = {&a, &step_ids[i]};
-    s = add_node(graph, &prev, parent, pgrid, PB, params, parent_shmem(a.nq));
+    s = add_node(graph, &prev, parent, pgrid, PB, params);
     if (s == DPO_OK && child) s = add_node(graph, &prev, child, cgrid, PB, params);
   }
   State* st = a.st;
@@ -214,6 +219,10 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid
     s = DPO_ERR_HIP;
   (void)hipGraphDestroy(graph);
   if (s != DPO_OK) return s;
+  if (!cached) {  // owned by the caller
+    *out = exec;
+    return DPO_OK;
+  }
   if ((int)r.graphs.size() >= kMaxCachedGraphs) {
     size_t victim = 0;
     for (size_t i = 1; i < r.graphs.size(); ++i)
@@ -236,6 +245,7 @@ struct SetRun {
   const void* child = nullptr;
   int pgrid = 0, cgrid = 0, steps = kDefaultSteps;
   hipStream_t stream = nullptr;
+  int32_t* qlist = nullptr;  // device: indices of the queries being admitted
 };
 
 dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_options& o,
@@ -267,6 +277,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.visit = (uint32_t*)(base + lay.visit);
   a.rec = (int4*)(base + lay.rec);
   a.rec_q = (int32_t*)(base + lay.rec_q);
+  a.qmap = (int32_t*)(base + lay.qmap);
   a.desc = (int4*)(base + lay.desc);
   a.stats = (unsigned long long*)(base + lay.stats);
   a.slots = (int32_t)slots;
@@ -278,7 +289,8 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
   a.count_stats = count_stats ? 1 : 0;
-  sr->pgrid = persistent_grid(r, sr->parent, parent_shmem(nq));
+  sr->qlist = (int32_t*)(base + lay.qlist);
+  sr->pgrid = persistent_grid(r, sr->parent);
   sr->cgrid = sr->child ? persistent_grid(r, sr->child) : 0;
   sr->steps = o.steps_per_replay ? o.steps_per_replay : kDefaultSteps;
   sr->stream = (hipStream_t)stream;
@@ -291,19 +303,47 @@ int init_grid(Runtime& r, int64_t work) {
   return (int)std::max<int64_t>(gsz, 1);
 }
 
-// Upload host query records [q_first, q_first + count) and start them.
-dpo_status admit(Runtime& r, SetRun& sr, const Query* hq, int32_t q_first, int32_t count,
+// Start the queries hlist[0 .. count) whose records are already in hq (host,
+// pinned): upload those records and the index list, then the admit kernels.
+dpo_status admit(Runtime& r, SetRun& sr, const Query* hq, const int32_t* hlist, int32_t count,
                  int32_t reset, int64_t work) {
   if (count <= 0) return DPO_OK;
-  if (hipMemcpyAsync(sr.a.q + q_first, hq + q_first, (size_t)count * sizeof(Query),
-                     hipMemcpyHostToDevice, sr.stream) != hipSuccess)
+  for (int32_t k = 0; k < count; ++k)
+    if (hipMemcpyAsync(sr.a.q + hlist[k], hq + hlist[k], sizeof(Query), hipMemcpyHostToDevice,
+                       sr.stream) != hipSuccess)
+      return DPO_ERR_HIP;
+  if (hipMemcpyAsync(sr.qlist, hlist, (size_t)count * 4, hipMemcpyHostToDevice, sr.stream) !=
+      hipSuccess)
     return DPO_ERR_HIP;
-  void* p1[] = {&sr.a, &q_first, &count, &reset};
+  int32_t* dl = sr.qlist;
+  void* p1[] = {&sr.a, &dl, &count, &reset};
   if (hipLaunchKernel(admit_kernel_ptr(sr.problem), dim3(init_grid(r, work)), dim3(PB), p1, 0,
                       sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
-  void* p2[] = {&sr.a, &q_first, &count};
+  void* p2[] = {&sr.a, &dl, &count};
   if (hipLaunchKernel(admit_sources_kernel_ptr(), dim3((unsigned)cdiv(count, PB)), dim3(PB), p2, 0,
+                      sr.stream) != hipSuccess)
+    return DPO_ERR_HIP;
+  return DPO_OK;
+}
+
+// Batch start: the whole table in one upload, then the admit kernels.
+dpo_status admit_all(Runtime& r, SetRun& sr, const Query* hq, const int32_t* hlist, int32_t nq,
+                     int64_t work) {
+  if (hipMemcpyAsync(sr.a.q, hq, (size_t)nq * sizeof(Query), hipMemcpyHostToDevice, sr.stream) !=
+      hipSuccess)
+    return DPO_ERR_HIP;
+  if (hipMemcpyAsync(sr.qlist, hlist, (size_t)nq * 4, hipMemcpyHostToDevice, sr.stream) !=
+      hipSuccess)
+    return DPO_ERR_HIP;
+  int32_t* dl = sr.qlist;
+  int32_t reset = 0;
+  void* p1[] = {&sr.a, &dl, &nq, &reset};
+  if (hipLaunchKernel(admit_kernel_ptr(sr.problem), dim3(init_grid(r, work)), dim3(PB), p1, 0,
+                      sr.stream) != hipSuccess)
+    return DPO_ERR_HIP;
+  void* p2[] = {&sr.a, &dl, &nq};
+  if (hipLaunchKernel(admit_sources_kernel_ptr(), dim3((unsigned)cdiv(nq, PB)), dim3(PB), p2, 0,
                       sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
   return DPO_OK;
@@ -382,8 +422,10 @@ dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_opt
   if (s != DPO_OK) return s;
   Query* hq = r.host_q;
   hq[0] = Query{0, g->n, 0, 0, o->threshold, o->coarsen, 0, source};
+  int32_t* hl = r.host_list;
+  hl[0] = 0;
   if ((s = start_set(r, sr)) != DPO_OK) return s;
-  if ((s = admit(r, sr, hq, 0, 1, 0, g->n)) != DPO_OK) return s;
+  if ((s = admit(r, sr, hq, hl, 1, 0, g->n)) != DPO_OK) return s;
   if ((s = run_to_completion(r, sr, g->n)) != DPO_OK) return s;
   return read_stats(r, sr, st);
 }
@@ -450,14 +492,292 @@ dpo_status traverse_batch(int problem, const dpo_arena* ar, const dpo_query* qs,
                   qs[i].source};
     slot += round32(n);
   }
+  int32_t* hl = r.host_list;
+  for (int32_t i = 0; i < nq; ++i) hl[i] = i;
   if ((s = start_set(r, sr)) != DPO_OK) return s;
-  if ((s = admit(r, sr, hq, 0, nq, 0, max_n)) != DPO_OK) return s;
+  if ((s = admit_all(r, sr, hq, hl, nq, max_n)) != DPO_OK) return s;
   if ((s = run_to_completion(r, sr, slots)) != DPO_OK) return s;
   return read_stats(r, sr, st);
 }
 
+
+// ------------------------------------------------------------ serving engine
+// Continuous batching: queries are admitted at replay boundaries while
+// others are running, as long as their output slots (footprint) and a query
+// table entry are free; finished queries are retired and their slots reused.
+struct Pending {
+  uint64_t ticket;
+  int32_t graph, source;
+  void* out;
+};
+
+struct Running {
+  bool used = false;
+  uint64_t ticket = 0;
+  void* out = nullptr;
+  int32_t n = 0;
+  int64_t slot0 = 0;
+  int64_t footprint = 0;
+};
+
 }  // namespace
 }  // namespace dpo
+
+struct dpo_engine {
+  int problem = dpo::PROB_BFS;
+  dpo_csr csr{};
+  std::vector<int32_t> vbase;
+  std::vector<dpo_options> bopts;
+  std::vector<int32_t> gbucket;
+  dpo::SetRun sr;
+  int32_t max_queries = 0;
+  int64_t max_slots = 0;
+  char* out_arena = nullptr;
+  std::map<int64_t, int64_t> free_slots;  // start -> length, 32-aligned
+  std::vector<dpo::Running> run;
+  std::vector<int32_t> free_q;
+  std::deque<dpo::Pending> pending;
+  std::deque<uint64_t> completed;
+  uint64_t next_ticket = 1;
+  int32_t running = 0;
+  bool inflight = false;
+  hipGraphExec_t exec = nullptr;
+  dpo::Query* hq = nullptr;   // pinned mirror of the device query table
+  int32_t* hlist = nullptr;   // pinned
+  uint32_t* hflags = nullptr; // pinned
+  int64_t max_n = 0;
+};
+
+namespace dpo {
+namespace {
+
+bool slots_alloc(dpo_engine* e, int64_t len, int64_t* start) {
+  for (auto it = e->free_slots.begin(); it != e->free_slots.end(); ++it) {
+    if (it->second >= len) {
+      *start = it->first;
+      const int64_t rest = it->second - len;
+      const int64_t nstart = it->first + len;
+      e->free_slots.erase(it);
+      if (rest > 0) e->free_slots[nstart] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void slots_free(dpo_engine* e, int64_t start, int64_t len) {
+  auto it = e->free_slots.emplace(start, len).first;
+  auto nx = std::next(it);
+  if (nx != e->free_slots.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    e->free_slots.erase(nx);
+  }
+  if (it != e->free_slots.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      e->free_slots.erase(it);
+    }
+  }
+}
+
+dpo_status engine_step(dpo_engine* e) {
+  Runtime& r = rt();
+  SetRun& sr = e->sr;
+  dpo_status s = DPO_OK;
+  if (e->inflight) {
+    if (hipStreamSynchronize(sr.stream) != hipSuccess) return DPO_ERR_HIP;
+    e->inflight = false;
+    if (e->hflags[2] != 0) return (dpo_status)(-(int32_t)e->hflags[2]);
+    // queries without frontier entries at the last level run have finished
+    const int32_t last_level = (int32_t)e->hflags[0] - 1;
+    const bool all_done = e->hflags[1] != 0;
+    int32_t retired = 0;
+    for (int32_t q = 0; q < e->max_queries; ++q) {
+      Running& ru = e->run[q];
+      if (!ru.used || !(all_done || e->hq[q].last < last_level)) continue;
+      const size_t bytes = (size_t)ru.n * 4;
+      if (hipMemcpyAsync(ru.out, e->out_arena + ru.slot0 * 4, bytes, hipMemcpyDeviceToDevice,
+                         sr.stream) != hipSuccess)
+        return DPO_ERR_HIP;
+      slots_free(e, ru.slot0, ru.footprint);
+      e->completed.push_back(ru.ticket);
+      ru = Running{};
+      e->free_q.push_back(q);
+      --e->running;
+      ++retired;
+    }
+    if (retired && hipStreamSynchronize(sr.stream) != hipSuccess) return DPO_ERR_HIP;
+  }
+  // admit in arrival order while a table entry and the footprint fit
+  int32_t count = 0;
+  const bool reset = e->running == 0;
+  int64_t work = 0;
+  while (!e->pending.empty() && !e->free_q.empty()) {
+    const Pending& p = e->pending.front();
+    const int32_t n = e->vbase[p.graph + 1] - e->vbase[p.graph];
+    int64_t slot0;
+    if (!slots_alloc(e, round32(n), &slot0)) break;
+    const int32_t q = e->free_q.back();
+    e->free_q.pop_back();
+    const dpo_options& bo = e->bopts[e->gbucket[p.graph]];
+    e->hq[q] = Query{(int32_t)slot0, n, e->vbase[p.graph], 0, bo.threshold, bo.coarsen, 0,
+                     p.source};
+    Running& ru = e->run[q];
+    ru.used = true;
+    ru.ticket = p.ticket;
+    ru.out = p.out;
+    ru.n = n;
+    ru.slot0 = slot0;
+    ru.footprint = round32(n);
+    e->hlist[count++] = q;
+    work = std::max<int64_t>(work, n);
+    ++e->running;
+    e->pending.pop_front();
+  }
+  if (count) {
+    if (reset) {
+      // nothing was running: restart the level sets (and their counters)
+      if ((s = start_set(r, sr)) != DPO_OK) return s;
+    }
+    if ((s = admit(r, sr, e->hq, e->hlist, count, 0, work)) != DPO_OK) return s;
+  }
+  if (e->running > 0) {
+    if (hipGraphLaunch(e->exec, sr.stream) != hipSuccess) return DPO_ERR_HIP;
+    if (hipMemcpyAsync(e->hflags, sr.a.st, 16, hipMemcpyDeviceToHost, sr.stream) != hipSuccess ||
+        hipMemcpyAsync(e->hq, sr.a.q, (size_t)e->max_queries * sizeof(Query),
+                       hipMemcpyDeviceToHost, sr.stream) != hipSuccess)
+      return DPO_ERR_HIP;
+    e->inflight = true;
+  }
+  return DPO_OK;
+}
+
+}  // namespace
+}  // namespace dpo
+
+extern "C" {
+
+size_t dpo_engine_workspace_bytes(const dpo_options* o, int32_t max_queries, int64_t max_slots) {
+  if (!o || dpo::check_options(*o) != DPO_OK || max_queries < 1 ||
+      max_queries > dpo::MAX_QUERIES || max_slots < 32 || max_slots > INT32_MAX)
+    return 0;
+  return dpo::layout_for(dpo::round32(max_slots), max_queries, *o).total;
+}
+
+dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_options* bucket_opts,
+                             int32_t nbuckets, const int32_t* graph_bucket, int32_t max_queries,
+                             int64_t max_slots, void* ws, size_t ws_bytes, void* out_arena,
+                             void* stream, dpo_engine** out) {
+  using namespace dpo;
+  if (!out || !bucket_opts || nbuckets < 1 || !ws || !out_arena || (kind != 0 && kind != 1))
+    return DPO_ERR_ARG;
+  *out = nullptr;
+  const int problem = kind == 0 ? PROB_BFS : PROB_SSSP;
+  dpo_status s = check_arena(arena, problem == PROB_SSSP);
+  if (s != DPO_OK) return s;
+  for (int32_t b = 0; b < nbuckets; ++b)
+    if ((s = check_options(bucket_opts[b])) != DPO_OK) return s;
+  if (max_queries < 1 || max_queries > MAX_QUERIES || max_slots < 32 || max_slots > INT32_MAX)
+    return DPO_ERR_ARG;
+  if (problem == PROB_SSSP && arena->csr.n > 16843009) return DPO_ERR_ARG;
+  max_slots = round32(max_slots);
+  if (ws_bytes < layout_for(max_slots, max_queries, bucket_opts[0]).total) return DPO_ERR_WORKSPACE;
+  if (graph_bucket)
+    for (int32_t g = 0; g < arena->ngraphs; ++g)
+      if (graph_bucket[g] < 0 || graph_bucket[g] >= nbuckets) return DPO_ERR_ARG;
+  Runtime& r = rt();
+  std::lock_guard<std::mutex> lock(r.mu);
+  if ((s = ensure_runtime(r)) != DPO_OK) return s;
+  dpo_engine* e = new dpo_engine();
+  e->problem = problem;
+  e->csr = arena->csr;
+  e->vbase.assign(arena->graph_vbase, arena->graph_vbase + arena->ngraphs + 1);
+  e->bopts.assign(bucket_opts, bucket_opts + nbuckets);
+  e->gbucket.assign(arena->ngraphs, 0);
+  if (graph_bucket) e->gbucket.assign(graph_bucket, graph_bucket + arena->ngraphs);
+  e->max_queries = max_queries;
+  e->max_slots = max_slots;
+  e->out_arena = (char*)out_arena;
+  e->free_slots[0] = max_slots;
+  e->run.assign(max_queries, Running{});
+  for (int32_t q = max_queries - 1; q >= 0; --q) e->free_q.push_back(q);
+  s = prepare_set(r, problem, &e->csr, bucket_opts[0], max_slots, max_queries, out_arena, ws,
+                  ws_bytes, stream, false, &e->sr);
+  void* p = nullptr;
+  if (s == DPO_OK &&
+      hipHostMalloc(&p, 64 + (size_t)max_queries * (sizeof(Query) + 4), hipHostMallocDefault) !=
+          hipSuccess)
+    s = DPO_ERR_HIP;
+  if (s == DPO_OK) {
+    e->hflags = (uint32_t*)p;
+    e->hq = (Query*)((char*)p + 64);
+    e->hlist = (int32_t*)(e->hq + max_queries);
+    std::memset(e->hq, 0, (size_t)max_queries * sizeof(Query));
+    s = get_exec(r, e->sr.parent, e->sr.child, e->sr.pgrid, e->sr.cgrid, e->sr.steps, e->sr.a,
+                 &e->exec, false);
+  }
+  if (s == DPO_OK) s = start_set(r, e->sr);
+  if (s == DPO_OK &&
+      hipMemcpyAsync(e->sr.a.q, e->hq, (size_t)max_queries * sizeof(Query), hipMemcpyHostToDevice,
+                     e->sr.stream) != hipSuccess)
+    s = DPO_ERR_HIP;
+  if (s == DPO_OK && hipStreamSynchronize(e->sr.stream) != hipSuccess) s = DPO_ERR_HIP;
+  if (s != DPO_OK) {
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (p) (void)hipHostFree(p);
+    delete e;
+    return s;
+  }
+  *out = e;
+  return DPO_OK;
+}
+
+dpo_status dpo_engine_submit(dpo_engine* e, int32_t graph, int32_t source, void* out,
+                             uint64_t* ticket) {
+  if (!e || !out || graph < 0 || graph >= (int32_t)e->vbase.size() - 1) return DPO_ERR_ARG;
+  const int32_t n = e->vbase[graph + 1] - e->vbase[graph];
+  if (source < 0 || source >= n) return DPO_ERR_SOURCE;
+  if (dpo::round32(n) > e->max_slots) return DPO_ERR_CAPACITY;
+  const uint64_t t = e->next_ticket++;
+  e->pending.push_back(dpo::Pending{t, graph, source, out});
+  if (ticket) *ticket = t;
+  return DPO_OK;
+}
+
+dpo_status dpo_engine_step(dpo_engine* e, int32_t* running, int32_t* pending) {
+  if (!e) return DPO_ERR_ARG;
+  dpo::Runtime& r = dpo::rt();
+  dpo_status s;
+  {
+    std::lock_guard<std::mutex> lock(r.mu);
+    s = dpo::engine_step(e);
+  }
+  if (running) *running = e->running;
+  if (pending) *pending = (int32_t)e->pending.size();
+  return s;
+}
+
+int32_t dpo_engine_poll(dpo_engine* e, uint64_t* tickets, int32_t cap) {
+  if (!e || !tickets || cap < 1) return 0;
+  int32_t k = 0;
+  while (k < cap && !e->completed.empty()) {
+    tickets[k++] = e->completed.front();
+    e->completed.pop_front();
+  }
+  return k;
+}
+
+void dpo_engine_destroy(dpo_engine* e) {
+  if (!e) return;
+  if (e->inflight) (void)hipStreamSynchronize(e->sr.stream);
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->hflags) (void)hipHostFree(e->hflags);
+  delete e;
+}
+
+}  // extern "C"
+
 
 extern "C" {
 

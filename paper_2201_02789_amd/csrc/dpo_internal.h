@@ -67,6 +67,7 @@ struct Args {
   uint32_t* visit;                 // BFS bitmap words / SSSP stamps, indexed by slot
   int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
   int32_t* rec_q;                  // [slots] query of each record
+  int32_t* qmap;                   // [slots / 32] query owning each 32-slot chunk
   int4* desc;                      // [NQD][desc_cap] {record base, records, block base, -}
   unsigned long long* stats;       // [MAX_GRID][NSTAT], one row per workgroup
   int32_t slots;                   // total output slots (sum of the queries' n)

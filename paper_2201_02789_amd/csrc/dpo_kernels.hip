@@ -317,15 +317,6 @@ __device__ __forceinline__ int32_t frontier_at(const Args& a, const int32_t* fin
   return fin[(size_t)lo * a.fcap + (i - s_fpre[lo])];
 }
 
-// Query owning slot s: largest q with slot0[q] <= s (table in LDS).
-__device__ __forceinline__ uint32_t query_of(const int32_t* s_q0, int32_t nq, int32_t s) {
-  uint32_t lo = 0, hi = (uint32_t)nq;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (s_q0[mid] <= s) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 // One parent thread: its query, vertex, row and parameters.
 struct Parent {
@@ -336,11 +327,10 @@ struct Parent {
 
 template <int P>
 __device__ __forceinline__ Parent load_parent(const Args& a, const int32_t* fin,
-                                              const uint32_t* s_fpre, const int32_t* s_q0,
-                                              uint32_t i, uint32_t L) {
+                                              const uint32_t* s_fpre, uint32_t i, uint32_t L) {
   Parent p;
   p.slot = frontier_at(a, fin, s_fpre, i);
-  p.q = query_of(s_q0, a.nq, p.slot);
+  p.q = (uint32_t)a.qmap[(uint32_t)p.slot >> 5];
   const Query Q = a.q[p.q];
   const int32_t vg = Q.vbase + (p.slot - Q.slot0);
   p.start = a.rp[vg];
@@ -359,7 +349,6 @@ __device__ __forceinline__ Parent load_parent(const Args& a, const int32_t* fin,
 // Pass 1 decides each parent (threshold), aggregates the launching ones and
 // writes their records (block barriers); pass 2 runs the thresholded parents'
 // serial children with no barrier, so waves do not wait on each other.
-// Dynamic LDS: the queries' first slots [nq] and one live bit per query.
 template <int P, int G>
 __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
@@ -367,9 +356,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ uint32_t s_scan[2 * NW];
   __shared__ uint32_t s_bc[NW + 8];
   __shared__ unsigned long long s_stats[NSTAT];
-  extern __shared__ int32_t s_dyn[];
-  int32_t* s_q0 = s_dyn;
-  uint32_t* s_live = (uint32_t*)(s_dyn + a.nq);
+  __shared__ uint32_t s_live[MAX_QUERIES / 32];  // queries seen at this level
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
@@ -389,7 +376,6 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     if (lane == 63) s_fpre[NQF + 1] = incl + prv->fcnt[NQF];
   }
   if (tid < NSTAT) s_stats[tid] = 0;
-  for (int i = tid; i < a.nq; i += PB) s_q0[i] = a.q[i].slot0;
   for (int i = tid; i < (a.nq + 31) / 32; i += PB) s_live[i] = 0;
   __syncthreads();
   const uint32_t F = s_fpre[NQF + 1];
@@ -423,7 +409,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       uint32_t du = 0, cg = 0;
       bool launch = false;
       if (i < F) {
-        const Parent p = load_parent<P>(a, fin, s_fpre, s_q0, i, L);
+        const Parent p = load_parent<P>(a, fin, s_fpre, i, L);
         start = p.start;
         deg = p.deg;
         q = (int32_t)p.q;
@@ -533,7 +519,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     int32_t start = 0, deg = 0;
     Elem e{0, 0, 0, 0, 0u};
     if (i < F) {
-      Parent p = load_parent<P>(a, fin, s_fpre, s_q0, i, L);
+      Parent p = load_parent<P>(a, fin, s_fpre, i, L);
       start = p.start;
       deg = p.deg;
       e = p.e;
@@ -757,20 +743,19 @@ __global__ __launch_bounds__(PB) void init_kernel(Args a) {
   for (uint32_t i = gid; i < sizeof(State) / 4; i += gsz) stw[i] = 0;
 }
 
-// Starts queries [q_first, q_first + q_count) at level index L = st->base:
-// their outputs set to "unreached" except the source, their visit words
-// cleared, their sources appended to the overflow queue of frontier L.
-// `reset` (host-known: the previous traversal set has finished) also clears
-// the level sets, whose fills are then stale.
+// Starts the queries list[0 .. count) at level index L = st->base: their
+// outputs set to "unreached" except the source, their visit words cleared and
+// their 32-slot chunks mapped to them.  `reset` (host-known: every earlier
+// query has finished) also clears the level sets, whose fills are then stale.
 template <int P>
-__global__ __launch_bounds__(PB) void admit_kernel(Args a, int32_t q_first, int32_t q_count,
+__global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, int32_t count,
                                                    int32_t reset) {
   State* st = a.st;
-  const uint32_t L = st->base;
   const uint32_t gsz = gridDim.x * PB;
   const uint32_t gid = blockIdx.x * PB + threadIdx.x;
-  for (int32_t k = 0; k < q_count; ++k) {
-    const Query Q = a.q[q_first + k];
+  for (int32_t k = 0; k < count; ++k) {
+    const int32_t qi = list[k];
+    const Query Q = a.q[qi];
     const uint32_t s0 = (uint32_t)Q.slot0, src = (uint32_t)Q.src;
     for (uint32_t v = gid; v < (uint32_t)Q.n; v += gsz) {
       if (P == PROB_BFS) {
@@ -780,10 +765,10 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, int32_t q_first, int3
         a.visit[s0 + v] = 0u;
       }
     }
-    if (P == PROB_BFS) {
-      const uint32_t words = ((uint32_t)Q.n + 31) / 32;
-      for (uint32_t i = gid; i < words; i += gsz)
-        a.visit[s0 / 32 + i] = (i == src >> 5) ? (1u << (src & 31)) : 0u;
+    const uint32_t words = ((uint32_t)Q.n + 31) / 32;
+    for (uint32_t i = gid; i < words; i += gsz) {
+      a.qmap[s0 / 32 + i] = qi;
+      if (P == PROB_BFS) a.visit[s0 / 32 + i] = (i == src >> 5) ? (1u << (src & 31)) : 0u;
     }
   }
   if (reset) {
@@ -797,14 +782,14 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, int32_t q_first, int3
 }
 
 // Second half of admission (after admit_kernel): sources into frontier L.
-__global__ void admit_sources_kernel(Args a, int32_t q_first, int32_t q_count) {
+__global__ void admit_sources_kernel(Args a, const int32_t* list, int32_t count) {
   State* st = a.st;
   const uint32_t L = st->base;
   LevelSet* ls = &st->set[(L + 2) % 3];  // fills of frontier L
   int32_t* fin = (L & 1) ? a.front1 : a.front0;
   const int32_t k = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (k < q_count) {
-    Query* Q = &a.q[q_first + k];
+  if (k < count) {
+    Query* Q = &a.q[list[k]];
     Q->lstart = (int32_t)L;
     Q->last = (int32_t)L;
     const uint32_t pos = atomicAdd(&ls->fcnt[NQF], 1u);

@@ -137,6 +137,24 @@ def lib():
         f.argtypes = [ctypes.POINTER(_Arena), ctypes.POINTER(_Query), ctypes.c_int32,
                       ctypes.POINTER(_Options), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(_Stats)]
+    L.dpo_engine_workspace_bytes.restype = ctypes.c_size_t
+    L.dpo_engine_workspace_bytes.argtypes = [ctypes.POINTER(_Options), ctypes.c_int32,
+                                             ctypes.c_int64]
+    L.dpo_engine_create.restype = ctypes.c_int32
+    L.dpo_engine_create.argtypes = [ctypes.POINTER(_Arena), ctypes.c_int32, ctypes.POINTER(_Options),
+                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.dpo_engine_submit.restype = ctypes.c_int32
+    L.dpo_engine_submit.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]
+    L.dpo_engine_step.restype = ctypes.c_int32
+    L.dpo_engine_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]
+    L.dpo_engine_poll.restype = ctypes.c_int32
+    L.dpo_engine_poll.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]
+    L.dpo_engine_destroy.restype = None
+    L.dpo_engine_destroy.argtypes = [ctypes.c_void_p]
     L.dpo_strerror.restype = ctypes.c_char_p
     L.dpo_strerror.argtypes = [ctypes.c_int32]
     _lib = L
@@ -310,6 +328,81 @@ def dpo_sssp_batch(arena: DeviceArena, queries, bucket_opts, dist, ws, stream=No
                    stats: bool = False):
     return _batch(lib().dpo_sssp_batch, "dpo_sssp_batch", arena, queries, bucket_opts, dist, ws,
                   stream, stats)
+
+
+class Engine:
+    """Continuous-batching engine (dpo_engine_*): kind "bfs" or "sssp".
+
+    Holds references to the arena, its workspace and output scratch so they
+    outlive the engine.
+    """
+
+    def __init__(self, arena: DeviceArena, kind: str, bucket_opts, graph_bucket=None,
+                 max_queries: int = 256, max_slots: int = 1 << 22, stream=None):
+        import torch
+        self.arena = arena
+        self.kind = kind
+        self.bucket_opts = list(bucket_opts)
+        ob = (_Options * len(self.bucket_opts))(*[o.c() for o in self.bucket_opts])
+        self._ob = ob
+        nbytes = lib().dpo_engine_workspace_bytes(ctypes.byref(ob[0]), max_queries, max_slots)
+        if nbytes == 0:
+            raise DpoError(DPO_ERR_ARG, "dpo_engine_workspace_bytes")
+        dev = arena.graph.row_ptr.device
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.scratch = torch.empty(((max_slots + 31) // 32) * 32, dtype=torch.int32, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._gb = None
+        gbp = None
+        if graph_bucket is not None:
+            self._gb = np.ascontiguousarray(graph_bucket, dtype=np.int32)
+            gbp = self._gb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self._arena_c = arena.c()
+        h = ctypes.c_void_p()
+        rc = lib().dpo_engine_create(ctypes.byref(self._arena_c), 0 if kind == "bfs" else 1, ob,
+                                     len(self.bucket_opts), gbp, max_queries, max_slots,
+                                     ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                     ctypes.c_void_p(self.scratch.data_ptr()),
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != DPO_OK:
+            raise DpoError(rc, "dpo_engine_create")
+        self.h = h
+        self._outs = {}
+
+    def submit(self, graph: int, source: int, out) -> int:
+        t = ctypes.c_uint64()
+        rc = lib().dpo_engine_submit(self.h, int(graph), int(source), ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.byref(t))
+        if rc != DPO_OK:
+            raise DpoError(rc, "dpo_engine_submit")
+        self._outs[t.value] = out  # keep the output alive until it is reported
+        return int(t.value)
+
+    def step(self):
+        run, pend = ctypes.c_int32(), ctypes.c_int32()
+        rc = lib().dpo_engine_step(self.h, ctypes.byref(run), ctypes.byref(pend))
+        if rc != DPO_OK:
+            raise DpoError(rc, "dpo_engine_step")
+        return run.value, pend.value
+
+    def poll(self, cap: int = 4096):
+        buf = (ctypes.c_uint64 * cap)()
+        k = lib().dpo_engine_poll(self.h, buf, cap)
+        done = [int(buf[i]) for i in range(k)]
+        for t in done:
+            self._outs.pop(t, None)
+        return done
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dpo_engine_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def as_uint32(t) -> np.ndarray:

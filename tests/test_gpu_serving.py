@@ -1,0 +1,86 @@
+"""GPU parity of the continuous-batching engine: queries admitted while
+others run, a footprint pool small enough that admission waits, and every
+result bit-identical to the oracle and to the same query run alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_02789_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2201_02789_amd import dpo  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def resident():
+    graphs = [gg.add_weights(gg.rmat(s, 16, 3000 + i, perm_seed=9000 + i), 500 + i)
+              for i, s in enumerate([9, 10, 11, 12, 13, 13])]
+    graphs.append(gg.add_weights(gg.path_graph(3000), 7))
+    arena, vbase = gg.pack_arena(graphs)
+    return graphs, dpo.DeviceArena(arena, vbase)
+
+
+
+
+@pytest.mark.parametrize("kind", ["bfs", "sssp"])
+@pytest.mark.parametrize("agg,steps", [(dpo.DPO_AGG_MULTIBLOCK, 2), (dpo.DPO_AGG_BLOCK, 5),
+                                       (dpo.DPO_AGG_NONE, 3)])
+def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps):
+    graphs, da = resident
+    rng = np.random.default_rng(11)
+    reqs = []
+    for _ in range(48):
+        g = int(rng.integers(0, len(graphs)))
+        reqs.append((g, int(gg.sample_sources(graphs[g], 1, int(rng.integers(1 << 30)))[0])))
+    bopts = [dpo.Options(threshold=16, coarsen=2, agg=agg, steps_per_replay=steps),
+             dpo.Options(threshold=64, coarsen=1, agg=agg, steps_per_replay=steps)]
+    gb = [0 if g.n < 2048 else 1 for g in graphs]
+    # pool of 12k slots: at most a few graphs at once, so admission waits on footprint
+    eng = dpo.Engine(da, kind, bopts, graph_bucket=gb, max_queries=8, max_slots=12 * 1024)
+    got_tickets = set()
+    outs = {}
+    pending = list(reqs)
+    for it in range(5000):
+        for g, s in pending[:3]:
+            o = torch.full((graphs[g].n,), -9, dtype=torch.int32, device="cuda")
+            outs[eng.submit(g, s, o)] = (g, s, o)
+        pending = pending[3:]
+        run, pend = eng.step()
+        got_tickets.update(eng.poll())
+        if not pending and run == 0 and pend == 0:
+            break
+    got_tickets.update(eng.poll())
+    eng.close()
+    torch.cuda.synchronize()
+    assert got_tickets == set(outs), "every submitted query completes"
+    for t, (g, s, o) in outs.items():
+        if kind == "bfs":
+            want, _ = oracle.bfs(graphs[g], s)
+            assert np.array_equal(o.cpu().numpy(), want), (t, g, s)
+        else:
+            want = oracle.dijkstra(graphs[g], s)
+            assert np.array_equal(dpo.as_uint32(o), want), (t, g, s)
+    # alone vs in the mix: the first few queries run on their own
+    for t in list(outs)[:4]:
+        g, s, o = outs[t]
+        dg = dpo.DeviceGraph.from_host(graphs[g])
+        lone, _ = (dpo.bfs if kind == "bfs" else dpo.sssp)(dg, s, bopts[gb[g]])
+        assert np.array_equal(lone.cpu().numpy(), o.cpu().numpy())
+
+
+def test_engine_rejects_oversized_and_bad_queries(resident):
+    graphs, da = resident
+    eng = dpo.Engine(da, "bfs", [dpo.Options()], max_queries=4, max_slots=1024)
+    o = torch.empty(graphs[3].n, dtype=torch.int32, device="cuda")
+    with pytest.raises(dpo.DpoError) as e:
+        eng.submit(3, 0, o)  # 2048 vertices never fit in 1024 slots
+    assert e.value.status == dpo.DPO_ERR_CAPACITY
+    with pytest.raises(dpo.DpoError) as e:
+        eng.submit(0, graphs[0].n, o)
+    assert e.value.status == dpo.DPO_ERR_SOURCE
+    eng.close()
