@@ -7,8 +7,13 @@ the HBM roofline of the level-step kernel, and the CPU oracle on host cores.
 A step is one pass of the whole hot path over the batch: one BFS from each of
 the 16 sources.  Prints ONE JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload bfs22|sssp21]
-                  [--sweep] [--no-cpu] [--no-baselines]
+  python bench.py [--steps K] [--warmup W] [--workload bfs22|sssp21|batch|serve]
+                  [--sweep] [--no-cpu] [--no-baselines] [--no-extras]
+
+The default run prints the s22 BFS line with two extra objects: "batched"
+(512 BFS over 64 R-MAT graphs of scales 10..18 in one launch sequence,
+per-bucket tuned) and "serving" (Poisson BFS/SSSP stream against 8 resident
+graphs, p50/p99 latency per offered rate).
 """
 import argparse
 import json
@@ -29,7 +34,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="bfs22", choices=["bfs22", "sssp21", "bfs12"])
+    p.add_argument("--workload", default="bfs22",
+                   choices=["bfs22", "sssp21", "bfs12", "batch", "serve"])
+    p.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
+    p.add_argument("--serve-seconds", type=float, default=0.5)
+    p.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
     p.add_argument("--threshold", type=int, default=None)
     p.add_argument("--coarsen", type=int, default=None)
     p.add_argument("--agg", default=None, help="none|wave|block|<k>-block")
@@ -173,6 +182,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dpo.lib()  # fail loudly if the HIP library is missing
 
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args, dpo, torch, full_line=True)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args, dpo, torch, full_line=True)), flush=True)
+        return
     wl = Workload(args.workload)
     dg = dpo.DeviceGraph.from_host(wl.g)
     tuned = dict(TUNED[args.workload])
@@ -258,7 +273,185 @@ def main():
         "speedup_vs_naive": round(gteps / baselines["naive"]["gteps"], 2) if baselines else None,
         "cpu_baseline": cpu,
     }
+    if not args.no_extras and args.workload == "bfs22":
+        del dg, wl
+        torch.cuda.empty_cache()
+        line["batched"] = bench_batch(args, dpo, torch)
+        line["serving"] = bench_serve(args, dpo, torch)
     print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- batched
+def bench_batch(args, dpo, torch, full_line=False):
+    """512 BFS over 64 R-MAT graphs (scales 10..18, edgefactor 8..32, 8
+    sources each) packed in one CSR arena; threshold and coarsening tuned per
+    size bucket (scales 10-12, 13-15, 16-18); one batch call per step."""
+    from paper_2201_02789_amd import autotune
+    from paper_2201_02789_amd import graphgen as gg
+    t0 = time.time()
+    graphs, queries = gg.batch_workload()
+    arena, vbase = gg.pack_arena(graphs)
+    da = dpo.DeviceArena(arena, vbase)
+    scales = [int(np.log2(g.n)) for g in graphs]
+    bucket = [0 if sc <= 12 else (1 if sc <= 15 else 2) for sc in scales]
+    log(f"[batch] {len(graphs)} graphs, {len(queries)} queries, arena n={arena.n} m={arena.m} "
+        f"({time.time() - t0:.1f}s)")
+    base = dpo.Options(threshold=32, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
+                       steps_per_replay=16)
+    tuned, traces = autotune.tune("bfs", da, graphs, queries, bucket, 3, base, max_runs=8, log=log)
+    qs = [(g, s, bucket[g]) for g, s in queries]
+    tot, slot0 = dpo.dpo_batch_slots(da, qs)
+    out = torch.empty(tot, dtype=torch.int32, device="cuda")
+    ws = torch.empty(dpo.dpo_batch_workspace_bytes(da, qs, tuned[0]), dtype=torch.uint8,
+                     device="cuda")
+    deg = [g.degrees() for g in graphs]
+    st = dpo.dpo_bfs_batch(da, qs, tuned, out, ws, stats=True)
+    host = out.cpu().numpy()
+    edges = 0
+    for i, (g, s, b) in enumerate(qs):
+        edges += int(deg[g][host[slot0[i]:slot0[i] + graphs[g].n] >= 0].sum())
+    steps, warm = max(1, args.steps), max(1, args.warmup)
+    for _ in range(warm):
+        dpo.dpo_bfs_batch(da, qs, tuned, out, ws)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        dpo.dpo_bfs_batch(da, qs, tuned, out, ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    res = {"traversals_per_s": round(len(qs) / (ms * 1e-3), 1), "ms_per_batch": round(ms, 3),
+           "gteps": round(edges / 2 / (ms * 1e-3) / 1e9, 3), "queries": len(qs),
+           "levels": st["levels"],
+           "tuned": [o.label() for o in tuned],
+           "tuning_runs": [len(t) for t in traces]}
+    # a sample of the same queries, one dpo_bfs call each on its own graph
+    one = dpo.Options(threshold=32, coarsen=1, steps_per_replay=16)
+    sub = qs[::8]
+    dgs = {g: dpo.DeviceGraph.from_host(graphs[g]) for g, _, _ in sub}
+    bufs = {g: (torch.empty(graphs[g].n, dtype=torch.int32, device="cuda"),
+                dpo.alloc_workspace(dgs[g], one)) for g in dgs}
+    for g, s, b in sub:  # warm-up: instantiates each graph's replay
+        dpo.dpo_bfs(dgs[g], int(s), one, *bufs[g])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for g, s, b in sub:
+        dpo.dpo_bfs(dgs[g], int(s), one, *bufs[g])
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t1) / len(sub)
+    res["one_by_one_traversals_per_s"] = round(1.0 / per, 1)
+    del dgs, bufs
+    # untuned: every bucket at the base point
+    qs0 = [(g, s, 0) for g, s, _ in qs]
+    dpo.dpo_bfs_batch(da, qs0, [base], out, ws)
+    torch.cuda.synchronize()
+    ev0.record()
+    dpo.dpo_bfs_batch(da, qs0, [base], out, ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    res["untuned_ms_per_batch"] = round(ev0.elapsed_time(ev1), 3)
+    log(f"[batch] {res}")
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_batch(graphs, queries)
+    if full_line:
+        return {"metric": "batched BFS traversals/s (512 over 64 R-MAT graphs, scales 10-18)",
+                "value": res["traversals_per_s"], "unit": "traversals/s", "n_gpus": 1,
+                "steps": steps, "warmup": warm, "ms_per_step": res["ms_per_batch"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+                "data": "synthetic", "config": {"workload": "batched BFS, 64 R-MAT graphs, 8 sources each"},
+                "batched": res}
+    return res
+
+
+def cpu_batch(graphs, queries, sample=64):
+    """Oracle BFS of a sample of the batch's queries on a pool of host threads."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    nthreads = os.cpu_count() or 1
+    sub = queries[::max(1, len(queries) // sample)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nthreads) as ex:
+        list(ex.map(lambda q: oracle.bfs(graphs[q[0]], q[1]), sub))
+    dt = time.perf_counter() - t0
+    return {"value": round(len(sub) / dt, 1), "unit": "traversals/s", "cores": nthreads,
+            "kind": "oracle", "sample": f"{len(sub)} of {len(queries)} queries, queue BFS, "
+                                        f"{nthreads} threads, {dt:.2f} s"}
+
+
+# ---------------------------------------------------------------- serving
+def bench_serve(args, dpo, torch, full_line=False):
+    """Poisson stream of BFS/SSSP queries (70/30) against 8 resident R-MAT
+    graphs (scales 14..20 and a second scale-20 graph, edgefactor 16, weights
+    U[1,255]); two continuous-batching engines on two streams."""
+    from paper_2201_02789_amd import graphgen as gg
+    t0 = time.time()
+    scales = [14, 15, 16, 17, 18, 19, 20, 20]
+    graphs = [gg.add_weights(gg.rmat(sc, 16, 3000 + i, perm_seed=9000 + i), 5000 + i)
+              for i, sc in enumerate(scales)]
+    arena, vbase = gg.pack_arena(graphs)
+    da = dpo.DeviceArena(arena, vbase)
+    pools = [gg.sample_sources(g, 64, 6000 + i) for i, g in enumerate(graphs)]
+    log(f"[serve] graphs ready, arena n={arena.n} m={arena.m} ({time.time() - t0:.1f}s)")
+    opts = [dpo.Options(threshold=32, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
+                        steps_per_replay=4)]
+    s_bfs, s_sssp = torch.cuda.Stream(), torch.cuda.Stream()
+    max_slots = 1 << 24
+    engines = {"bfs": dpo.Engine(da, "bfs", opts, max_queries=256, max_slots=max_slots,
+                                 stream=s_bfs),
+               "sssp": dpo.Engine(da, "sssp", opts, max_queries=256, max_slots=max_slots,
+                                  stream=s_sssp)}
+    sinks = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in graphs]
+    rates = [int(x) for x in args.rates.split(",")]
+    results = []
+    for lam in rates:
+        rng = np.random.default_rng(7 + lam)
+        nq = max(50, min(int(lam * args.serve_seconds), 25000))
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=nq))
+        kinds = np.where(rng.random(nq) < 0.7, "bfs", "sssp")
+        gsel = rng.integers(0, len(graphs), size=nq)
+        ssel = rng.integers(0, 64, size=nq)
+        tick = {"bfs": {}, "sssp": {}}
+        lat = np.full(nq, np.nan)
+        nxt = 0
+        done = 0
+        t_start = time.perf_counter()
+        while done < nq:
+            now = time.perf_counter() - t_start
+            while nxt < nq and arr[nxt] <= now:
+                k = kinds[nxt]
+                g = int(gsel[nxt])
+                t = engines[k].submit(g, int(pools[g][ssel[nxt]]), sinks[g])
+                tick[k][t] = nxt
+                nxt += 1
+            for k, e in engines.items():
+                e.step()
+                for t in e.poll():
+                    i = tick[k].pop(t)
+                    lat[i] = time.perf_counter() - t_start - arr[i]
+                    done += 1
+            if time.perf_counter() - t_start > 60:
+                break
+        wall = time.perf_counter() - t_start
+        ok = ~np.isnan(lat)
+        r = {"offered_qps": lam, "queries": int(ok.sum()),
+             "achieved_qps": round(float(ok.sum()) / max(wall, arr[-1]), 1),
+             "p50_ms": round(float(np.percentile(lat[ok], 50)) * 1e3, 3),
+             "p99_ms": round(float(np.percentile(lat[ok], 99)) * 1e3, 3)}
+        results.append(r)
+        log(f"[serve] {r}")
+    for e in engines.values():
+        e.close()
+    if full_line:
+        best = max(results, key=lambda r: r["achieved_qps"])
+        return {"metric": "serving q/s and p99 latency (BFS/SSSP 70/30, 8 resident R-MAT graphs)",
+                "value": best["achieved_qps"], "unit": "q/s", "n_gpus": 1, "steps": len(rates),
+                "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+                "config": {"workload": "Poisson BFS/SSSP 70/30, scales 14..20 + second 20"},
+                "serving": results}
+    return {"rates": results, "graphs": "R-MAT scales 14..20 + second 20, ef 16",
+            "mix": "70% BFS / 30% SSSP", "steps_per_replay": 4, "max_slots": max_slots}
 
 
 def sweep(dpo, torch, wl, dg):

@@ -1,0 +1,121 @@
+"""Per-size-bucket tuning of threshold and coarsening for batched traversals.
+
+Sec. VIII-C of the paper reports that the best threshold is usually the one
+that leaves about 6,000-8,000 child-grid launches, that performance is not
+sensitive to the coarsening factor once it is large enough, that warp
+granularity is never the best, and that a handful of runs finds a point close
+to the best.  The tuner follows that: for each bucket it starts from the
+threshold whose launch count (parents of degree >= T, summed over the bucket's
+queries) is closest to the 6,000-8,000 band, then takes greedy steps through a
+small (T, CF) grid, timing the batch restricted to that bucket, and stops when
+no neighbour is faster or after `max_runs` timed points.  The result can be
+saved as JSON and reloaded, so a tuned table is reused across runs.
+"""
+from __future__ import annotations
+
+import json
+import time
+from dataclasses import asdict
+
+import numpy as np
+
+from . import dpo
+
+T_GRID = (0, 8, 32, 128, 512, 2048)
+CF_GRID = (1, 2, 4, 8)
+LAUNCH_BAND = (6000, 8000)
+
+
+def heuristic_threshold(graphs, queries) -> int:
+    """T in T_GRID whose launch count over the queries' graphs is nearest the band.
+
+    Every reached vertex is a parent once per traversal; parents of degree
+    >= T launch.  Reachability is not known before running, so all vertices of
+    a query's graph are counted (an upper bound; the graphs are one component
+    plus isolated vertices, which have degree 0 and never launch)."""
+    target = sum(LAUNCH_BAND) / 2
+    counts = {}
+    for T in T_GRID:
+        c = 0
+        for g, _s in queries:
+            d = graphs[g].degrees()
+            c += int(np.count_nonzero(d >= max(T, 1)))
+        counts[T] = c
+    return min(T_GRID, key=lambda T: abs(np.log((counts[T] + 1) / target)))
+
+
+def _time_batch(kind, arena, queries, opts, reps=2):
+    import torch
+    tot, _ = dpo.dpo_batch_slots(arena, queries)
+    out = torch.empty(tot, dtype=torch.int32, device="cuda")
+    ws = torch.empty(dpo.dpo_batch_workspace_bytes(arena, queries, opts), dtype=torch.uint8,
+                     device="cuda")
+    f = dpo.dpo_bfs_batch if kind == "bfs" else dpo.dpo_sssp_batch
+    f(arena, queries, [opts], out, ws)  # warm-up (also instantiates the graph)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        f(arena, queries, [opts], out, ws)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune_bucket(kind, arena, graphs, queries, base: dpo.Options, max_runs: int = 10, log=None):
+    """Returns (best Options, [(label, seconds)]) for one bucket's queries."""
+    qs = [(g, s, 0) for g, s in queries]
+    T0 = heuristic_threshold(graphs, queries)
+    ti, ci = T_GRID.index(T0), CF_GRID.index(1)
+    seen = {}
+
+    def measure(i, j):
+        if (i, j) not in seen:
+            o = dpo.Options(**{**asdict(base), "threshold": T_GRID[i], "coarsen": CF_GRID[j]})
+            seen[(i, j)] = _time_batch(kind, arena, qs, o)
+            if log:
+                log(f"[tune] {kind} bucket T={T_GRID[i]} CF={CF_GRID[j]}: {seen[(i, j)] * 1e3:.3f} ms")
+        return seen[(i, j)]
+
+    cur = measure(ti, ci)
+    while len(seen) < max_runs:
+        nbrs = [(ti + di, ci + dj) for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1))
+                if 0 <= ti + di < len(T_GRID) and 0 <= ci + dj < len(CF_GRID)]
+        nbrs = [p for p in nbrs if p not in seen][: max_runs - len(seen)]
+        if not nbrs:
+            break
+        times = [(measure(*p), p) for p in nbrs]
+        t, p = min(times)
+        if t >= cur:
+            break
+        cur, (ti, ci) = t, p
+    best = dpo.Options(**{**asdict(base), "threshold": T_GRID[ti], "coarsen": CF_GRID[ci]})
+    trace = [(f"T{T_GRID[i]}-CF{CF_GRID[j]}", v) for (i, j), v in seen.items()]
+    return best, trace
+
+
+def tune(kind, arena, graphs, queries, bucket_of_graph, nbuckets, base: dpo.Options,
+         max_runs: int = 10, log=None):
+    """Tunes every bucket; returns the per-bucket Options list and the traces."""
+    opts, traces = [], []
+    for b in range(nbuckets):
+        qb = [(g, s) for g, s in queries if bucket_of_graph[g] == b]
+        if not qb:
+            opts.append(base)
+            traces.append([])
+            continue
+        o, tr = tune_bucket(kind, arena, graphs, qb, base, max_runs, log)
+        opts.append(o)
+        traces.append(tr)
+    return opts, traces
+
+
+def save(path, opts, meta=None):
+    with open(path, "w") as f:
+        json.dump({"buckets": [asdict(o) for o in opts], "meta": meta or {}}, f, indent=1)
+
+
+def load(path):
+    with open(path) as f:
+        d = json.load(f)
+    return [dpo.Options(**o) for o in d["buckets"]]
