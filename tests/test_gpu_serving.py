@@ -20,7 +20,7 @@ from paper_2201_02789_amd import dpo  # noqa: E402
 def resident():
     graphs = [gg.add_weights(gg.rmat(s, 16, 3000 + i, perm_seed=9000 + i), 500 + i)
               for i, s in enumerate([9, 10, 11, 12, 13, 13])]
-    graphs.append(gg.add_weights(gg.path_graph(3000), 7))
+    graphs.append(gg.add_weights(gg.path_graph(300), 7))  # 300 levels from an end
     arena, vbase = gg.pack_arena(graphs)
     return graphs, dpo.DeviceArena(arena, vbase)
 
@@ -45,7 +45,9 @@ def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps):
     got_tickets = set()
     outs = {}
     pending = list(reqs)
-    for it in range(5000):
+    import time
+    t_end = time.time() + 60
+    while time.time() < t_end:
         for g, s in pending[:3]:
             o = torch.full((graphs[g].n,), -9, dtype=torch.int32, device="cuda")
             outs[eng.submit(g, s, o)] = (g, s, o)
