@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-baselines", action="store_true")
     p.add_argument("--cpu-sources", type=int, default=4)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a plain 512 MiB device copy (counter calibration)")
     return p.parse_args()
 
 
@@ -180,6 +182,17 @@ def main():
     import torch
     from paper_2201_02789_amd import dpo
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale between those counters and bytes
+        n = (512 << 20) // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+        return
     dpo.lib()  # fail loudly if the HIP library is missing
 
     if args.workload == "batch":
