@@ -27,8 +27,8 @@ constexpr int kMaxCachedGraphs = 64;
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t state, queries, qlist, qmap, full, grp_packed, grp_done, front0, front1, visit, rec, rec_q,
-      desc, stats, total;
+  size_t state, queries, qlist, qmap, grp_packed, grp_done, front0, front1, visit, rec, rec_q, desc,
+      stats, total;
   int32_t ngroups_cap, desc_cap, fcap;
 };
 
@@ -69,7 +69,6 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.queries = off; off = align_up(off + (size_t)nq * sizeof(Query));
   L.qlist = off; off = align_up(off + (size_t)nq * 4);
   L.qmap = off; off = align_up(off + (size_t)cdiv(slots, 32) * 4);
-  L.full = off; off = align_up(off + (size_t)cdiv(slots, 1024) * 4);
   L.grp_packed = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 8);
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
   L.front0 = off; off = align_up(off + fslots * 4);
@@ -209,8 +208,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid
     step_ids[i] = (uint32_t)i;
     void* params[] = {&a, &step_ids[i]};
     s = add_node(graph, &prev, parent, pgrid, PB, params);
-    if (s == DPO_OK && child)
-      s = add_node(graph, &prev, child, cgrid, PB, params, a.full_lds ? FULL_LDS_WORDS * 4 : 0);
+    if (s == DPO_OK && child) s = add_node(graph, &prev, child, cgrid, PB, params);
   }
   State* st = a.st;
   uint32_t k = (uint32_t)steps;
@@ -280,8 +278,6 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.rec = (int4*)(base + lay.rec);
   a.rec_q = (int32_t*)(base + lay.rec_q);
   a.qmap = (int32_t*)(base + lay.qmap);
-  a.full = (uint32_t*)(base + lay.full);
-  a.full_lds = (problem == PROB_BFS && cdiv(slots, 1024) <= FULL_LDS_WORDS) ? 1 : 0;
   a.desc = (int4*)(base + lay.desc);
   a.stats = (unsigned long long*)(base + lay.stats);
   a.slots = (int32_t)slots;
@@ -295,7 +291,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.count_stats = count_stats ? 1 : 0;
   sr->qlist = (int32_t*)(base + lay.qlist);
   sr->pgrid = persistent_grid(r, sr->parent);
-  sr->cgrid = sr->child ? persistent_grid(r, sr->child, a.full_lds ? FULL_LDS_WORDS * 4 : 0) : 0;
+  sr->cgrid = sr->child ? persistent_grid(r, sr->child) : 0;
   sr->steps = o.steps_per_replay ? o.steps_per_replay : kDefaultSteps;
   sr->stream = (hipStream_t)stream;
   return DPO_OK;

@@ -12,9 +12,7 @@ constexpr int NQD = 8;           // descriptor queues (one per XCD: queue = virt
 constexpr int NQF = 64;          // frontier queues (queue = workgroup % 64), plus one overflow
 constexpr int MAX_GRID = 4096;   // persistent grid cap (rows of the per-workgroup counters)
 constexpr int NSTAT = 8;
-constexpr int MAX_QUERIES = 4096;  // per-query live bits are kept in LDS
-constexpr int FULL_LDS_WORDS = 4096;  // BFS word-full map staged in LDS (covers 4M slots)
-constexpr int FULL_MIN_BLOCKS = 4096; // stage it only for levels with this many child blocks
+constexpr int MAX_QUERIES = 4096;  // per-query tables are staged in LDS
 
 enum { PROB_BFS = 0, PROB_SSSP = 1 };
 enum { AGG_NONE = 0, AGG_WAVE = 1, AGG_BLOCK = 2, AGG_MULTI = 3, AGG_FLAT = 4 };
@@ -70,7 +68,6 @@ struct Args {
   int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
   int32_t* rec_q;                  // [slots] query of each record
   int32_t* qmap;                   // [slots / 32] query owning each 32-slot chunk
-  uint32_t* full;                  // [slots / 1024] BFS: bit w set once visit word w is all ones
   int4* desc;                      // [NQD][desc_cap] {record base, records, block base, -}
   unsigned long long* stats;       // [MAX_GRID][NSTAT], one row per workgroup
   int32_t slots;                   // total output slots (sum of the queries' n)
@@ -82,7 +79,7 @@ struct Args {
   int32_t desc_cap;                // per descriptor queue
   int32_t fcap;                    // per frontier queue
   int32_t count_stats;
-  int32_t full_lds;                // child kernels get FULL_LDS_WORDS of dynamic LDS
+  int32_t pad;
 };
 
 const void* parent_kernel_ptr(int problem, int gran);

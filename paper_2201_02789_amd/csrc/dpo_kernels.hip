@@ -191,8 +191,7 @@ struct Elem {
 template <int P, int U>
 __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U],
                                             const uint32_t (&w)[U], const Elem (&c)[U],
-                                            uint32_t L, int32_t (&out)[U],
-                                            const uint32_t* s_full = nullptr) {
+                                            uint32_t L, int32_t (&out)[U]) {
   int32_t sl[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -205,33 +204,14 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
     out[u] = -1;
   }
   if (P == PROB_BFS) {
-    // a visit word whose 32 bits are all set is known from the LDS copy of the
-    // word-full map (it may be stale, which only costs a global probe)
-    if (s_full) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (sl[u] >= 0) {
-          const uint32_t wi = (uint32_t)sl[u] >> 5;
-          if ((s_full[wi >> 5] >> (wi & 31)) & 1u) sl[u] = -1;
-        }
-      }
-    }
     uint32_t word[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? a.visit[(uint32_t)sl[u] >> 5] : ~0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t bit = 1u << (sl[u] & 31);
-      if (sl[u] >= 0 && !(word[u] & bit)) {
-        const uint32_t old = atomicOr(&a.visit[(uint32_t)sl[u] >> 5], bit);
-        if ((old | bit) == ~0u) {  // this claim completed the word
-          const uint32_t wi = (uint32_t)sl[u] >> 5;
-          atomicOr(&a.full[wi >> 5], 1u << (wi & 31));
-        }
-        word[u] = old;
-      } else {
-        word[u] = ~0u;
-      }
+      if (sl[u] >= 0 && !(word[u] & bit)) word[u] = atomicOr(&a.visit[(uint32_t)sl[u] >> 5], bit);
+      else word[u] = ~0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -609,7 +589,6 @@ __device__ __forceinline__ Window load_window(const Args& a, uint32_t base, uint
 // search and the following ones by advancing along the scanned offsets.
 template <int P>
 __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
-  extern __shared__ uint32_t s_full[];  // FULL_LDS_WORDS when the launch provides it
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_bc[NW + 8];
   __shared__ uint32_t s_qpre[NQD + 1];
@@ -643,14 +622,6 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   Counters cn{0, 0, 0, 0, 0, 0, 0};
   Stage s{s_stage[wave], 0u};
   const uint32_t CB = (uint32_t)a.CB;
-  // big levels: stage the word-full map in LDS (block-uniform decision)
-  const uint32_t full_words = ((uint32_t)a.slots + 1023) / 1024;
-  const bool use_full = P == PROB_BFS && a.full_lds && B >= (uint32_t)FULL_MIN_BLOCKS;
-  if (use_full) {
-    for (uint32_t i = tid; i < full_words; i += PB) s_full[i] = a.full[i];
-    __syncthreads();
-  }
-  const uint32_t* sf = use_full ? s_full : nullptr;
 
   if (t0 < t1) {
     // disaggregation of the first block (Sec. V-A): queue, descriptor, record
@@ -729,7 +700,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
         w[u] = (P == PROB_SSSP && on) ? a.w[e0[u] + lane] : 0u;
         if (on) ++cn.echild;
       }
-      visit_batch<P, U>(a, v, w, c, L, out, sf);
+      visit_batch<P, U>(a, v, w, c, L, out);
 #pragma unroll
       for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
       // refill the record window when it is used up
@@ -795,27 +766,9 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
       }
     }
     const uint32_t words = ((uint32_t)Q.n + 31) / 32;
-    for (uint32_t i = gid; i < words; i += gsz) a.qmap[s0 / 32 + i] = qi;
-    if (P == PROB_BFS) {
-      // Visit words, 64 vertices per wave step (two words per ballot).
-      // Vertices without edges are never anyone's neighbour, so marking them
-      // (and the padding slots) visited changes no result but lets words fill
-      // up; the source is visited.
-      const uint32_t lane = threadIdx.x & 63, gw = gid >> 6, nwv = gsz >> 6;
-      for (uint32_t c = gw; c * 64 < (uint32_t)Q.n; c += nwv) {
-        const uint32_t v = c * 64 + lane;
-        bool mark = true;
-        if (v < (uint32_t)Q.n && v != src) mark = a.rp[Q.vbase + v + 1] == a.rp[Q.vbase + v];
-        const unsigned long long m = __ballot(mark);
-        const uint32_t w0 = s0 / 32 + 2 * c;
-        if (lane < 2 && 2 * c + lane < words) {
-          const uint32_t wv = lane ? (uint32_t)(m >> 32) : (uint32_t)m;
-          const uint32_t wi = w0 + lane;
-          a.visit[wi] = wv;
-          if (wv == ~0u) atomicOr(&a.full[wi >> 5], 1u << (wi & 31));
-          else atomicAnd(&a.full[wi >> 5], ~(1u << (wi & 31)));
-        }
-      }
+    for (uint32_t i = gid; i < words; i += gsz) {
+      a.qmap[s0 / 32 + i] = qi;
+      if (P == PROB_BFS) a.visit[s0 / 32 + i] = (i == src >> 5) ? (1u << (src & 31)) : 0u;
     }
   }
   if (reset) {
