@@ -65,7 +65,9 @@ typedef enum {
   DPO_AGG_WAVE = 1,       /* aggregation over the 64 parents of a wave
                              (the paper's warp granularity, Sec. II-B)          */
   DPO_AGG_BLOCK = 2,      /* over the 256 parents of a workgroup (Sec. II-B)    */
-  DPO_AGG_MULTIBLOCK = 3  /* over groups of agg_blocks workgroups (Sec. V-A)    */
+  DPO_AGG_MULTIBLOCK = 3, /* over groups of agg_blocks workgroups (Sec. V-A)    */
+  DPO_AGG_GRID = 4        /* over the whole parent grid of a level (Sec. II-B):
+                             one aggregated grid per level                      */
 } dpo_agg;
 
 typedef struct {
@@ -79,6 +81,10 @@ typedef struct {
   int32_t agg_blocks;       /* k >= 2 for DPO_AGG_MULTIBLOCK (e.g. 4 or 16)         */
   int32_t child_block;      /* original child block size bDim in {64, 128, 256}    */
   int32_t steps_per_replay; /* level steps per HIP-graph replay; 0 = 16            */
+  int32_t agg_threshold;    /* aggregation threshold (Sec. V-B), wave and block
+                               granularity only: when fewer than this many parents
+                               of the wave / block launch, each launches its own
+                               grid instead of joining an aggregated one; 0 = off */
 } dpo_options;
 
 typedef struct {
@@ -104,7 +110,7 @@ typedef struct {
 } dpo_stats;
 
 /* Fills *o with the defaults: nested, T = 128, CF = 8, 4-block aggregation,
- * child block 256, 16 steps per replay. */
+ * child block 256, 16 steps per replay, no aggregation threshold. */
 void dpo_default_options(dpo_options* o);
 
 /* Device workspace bytes needed by dpo_bfs / dpo_sssp on a graph with g->n

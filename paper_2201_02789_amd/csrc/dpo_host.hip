@@ -32,6 +32,9 @@ struct Layout {
   int32_t ngroups_cap, desc_cap, fcap;
 };
 
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t round32(int64_t x) { return (x + 31) & ~(int64_t)31; }
+
 int gran_of(const dpo_options& o) {
   if (o.mode == DPO_MODE_FLAT) return AGG_FLAT;
   switch (o.agg) {
@@ -39,23 +42,30 @@ int gran_of(const dpo_options& o) {
     case DPO_AGG_WAVE: return AGG_WAVE;
     case DPO_AGG_BLOCK: return AGG_BLOCK;
     case DPO_AGG_MULTIBLOCK: return AGG_MULTI;
+    case DPO_AGG_GRID: return AGG_MULTI;  // one group holding every virtual block
     default: return -1;
   }
 }
 
-int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-int64_t round32(int64_t x) { return (x + 31) & ~(int64_t)31; }
+// Blocks per multi-block group: agg_blocks, or every virtual block of the level
+// for grid granularity.
+int64_t group_blocks(const dpo_options& o, int64_t slots) {
+  return o.agg == DPO_AGG_GRID ? std::max<int64_t>(cdiv(slots, PB), 1) : o.agg_blocks;
+}
+
 
 // Workspace for `slots` output slots (frontier entries) and `nq` queries.
 Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   Layout L{};
   const int gran = gran_of(o);
   const int64_t nvb = cdiv(slots, PB);
-  const int64_t k = (gran == AGG_MULTI) ? o.agg_blocks : 1;
+  const int64_t k = (gran == AGG_MULTI) ? group_blocks(o, slots) : 1;
   L.ngroups_cap = (gran == AGG_MULTI) ? (int32_t)cdiv(nvb, k) : 1;
   // descriptors per queue: virtual block vb publishes to queue vb % NQD
   // (multi-block group g to queue g % NQD)
-  switch (gran) {
+  // an aggregation threshold lets every parent of a wave / block launch alone
+  const bool solo = o.agg_threshold > 0 && (gran == AGG_WAVE || gran == AGG_BLOCK);
+  switch (solo ? AGG_NONE : gran) {
     case AGG_NONE: L.desc_cap = (int32_t)(PB * cdiv(nvb, NQD)); break;
     case AGG_WAVE: L.desc_cap = (int32_t)(NW * cdiv(nvb, NQD)); break;
     case AGG_BLOCK: L.desc_cap = (int32_t)cdiv(nvb, NQD); break;
@@ -87,7 +97,8 @@ dpo_status check_options(const dpo_options& o) {
   if (o.threshold < 0) return DPO_ERR_ARG;
   if (o.coarsen != 1 && o.coarsen != 2 && o.coarsen != 4 && o.coarsen != 8 && o.coarsen != 16)
     return DPO_ERR_ARG;
-  if (o.agg < DPO_AGG_NONE || o.agg > DPO_AGG_MULTIBLOCK) return DPO_ERR_ARG;
+  if (o.agg < DPO_AGG_NONE || o.agg > DPO_AGG_GRID) return DPO_ERR_ARG;
+  if (o.agg_threshold < 0) return DPO_ERR_ARG;
   if (o.agg == DPO_AGG_MULTIBLOCK && (o.agg_blocks < 2 || o.agg_blocks > 1024)) return DPO_ERR_ARG;
   if (o.child_block != 64 && o.child_block != 128 && o.child_block != 256) return DPO_ERR_ARG;
   if (o.steps_per_replay < 0 || o.steps_per_replay > 1024) return DPO_ERR_ARG;
@@ -284,7 +295,8 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.m = g->m;
   a.nq = nq;
   a.CB = o.child_block;
-  a.k = (gran == AGG_MULTI) ? o.agg_blocks : 1;
+  a.k = (gran == AGG_MULTI) ? (int32_t)group_blocks(o, slots) : 1;
+  a.agg_threshold = o.agg_threshold;
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
@@ -790,6 +802,7 @@ void dpo_default_options(dpo_options* o) {
   o->agg_blocks = 4;
   o->child_block = 256;
   o->steps_per_replay = 0;
+  o->agg_threshold = 0;
 }
 
 size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o) {

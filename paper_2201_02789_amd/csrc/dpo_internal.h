@@ -79,7 +79,8 @@ struct Args {
   int32_t desc_cap;                // per descriptor queue
   int32_t fcap;                    // per frontier queue
   int32_t count_stats;
-  int32_t pad;
+  int32_t agg_threshold;           // wave / block granularity: fewer launching parents
+                                   // than this launch individually (Sec. V-B)
 };
 
 const void* parent_kernel_ptr(int problem, int gran);

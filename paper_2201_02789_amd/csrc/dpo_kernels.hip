@@ -433,16 +433,25 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         }
       } else if (G == AGG_WAVE) {
         const unsigned long long m = __ballot(launch);
-        if (m) {  // wave-uniform
+        const uint32_t nrec = (uint32_t)__popcll(m);
+        const uint32_t seg = vb * PB + wave * 64;
+        if (m && nrec < (uint32_t)a.agg_threshold) {
+          // too few participants (Sec. V-B): each parent launches its own grid
+          if (launch) {
+            a.rec[seg + lane_rank(m)] = make_int4(start, deg, 0, (int32_t)du);
+            a.rec_q[seg + lane_rank(m)] = q;
+            publish(a, cur, vb % NQD, seg + lane_rank(m), 1u, cg);
+            ++cn.desc;
+          }
+        } else if (m) {  // wave-uniform
           const uint32_t incl = wave_incl_scan(cg, lane);
           const uint32_t total = __shfl(incl, 63, 64);
-          const uint32_t seg = vb * PB + wave * 64;
           if (launch) {
             a.rec[seg + lane_rank(m)] = make_int4(start, deg, (int32_t)(incl - cg), (int32_t)du);
             a.rec_q[seg + lane_rank(m)] = q;
           }
           if (lane == 0) {
-            publish(a, cur, vb % NQD, seg, (uint32_t)__popcll(m), total);
+            publish(a, cur, vb % NQD, seg, nrec, total);
             ++cn.desc;
           }
         }
@@ -464,14 +473,25 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         }
         if (G == AGG_BLOCK) {
           const uint32_t seg = vb * PB;
-          if (launch) {
-            a.rec[seg + roff + lane_rank(m)] =
-                make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
-            a.rec_q[seg + roff + lane_rank(m)] = q;
-          }
-          if (tid == 0 && nrec_b) {
-            publish(a, cur, vb % NQD, seg, nrec_b, total_b);
-            ++cn.desc;
+          if (nrec_b < (uint32_t)a.agg_threshold) {
+            // too few participants (Sec. V-B): each parent launches its own grid
+            if (launch) {
+              const uint32_t slot = seg + roff + lane_rank(m);
+              a.rec[slot] = make_int4(start, deg, 0, (int32_t)du);
+              a.rec_q[slot] = q;
+              publish(a, cur, vb % NQD, slot, 1u, cg);
+              ++cn.desc;
+            }
+          } else {
+            if (launch) {
+              a.rec[seg + roff + lane_rank(m)] =
+                  make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
+              a.rec_q[seg + roff + lane_rank(m)] = q;
+            }
+            if (tid == 0 && nrec_b) {
+              publish(a, cur, vb % NQD, seg, nrec_b, total_b);
+              ++cn.desc;
+            }
           }
           __syncthreads();  // s_scan reuse
         } else {  // AGG_MULTI: group of k consecutive virtual blocks (Sec. V-A)

@@ -30,6 +30,7 @@ DPO_AGG_NONE = 0
 DPO_AGG_WAVE = 1
 DPO_AGG_BLOCK = 2
 DPO_AGG_MULTIBLOCK = 3
+DPO_AGG_GRID = 4
 
 UNREACHED_LEVEL = -1
 UNREACHED_DIST = 0xFFFFFFFF
@@ -45,7 +46,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("threshold", ctypes.c_int32),
                 ("coarsen", ctypes.c_int32), ("agg", ctypes.c_int32),
                 ("agg_blocks", ctypes.c_int32), ("child_block", ctypes.c_int32),
-                ("steps_per_replay", ctypes.c_int32)]
+                ("steps_per_replay", ctypes.c_int32), ("agg_threshold", ctypes.c_int32)]
 
 
 class _Csr(ctypes.Structure):
@@ -80,6 +81,7 @@ class Options:
     agg_blocks: int = 4
     child_block: int = 256
     steps_per_replay: int = 0
+    agg_threshold: int = 0
 
     def c(self) -> _Options:
         return _Options(*(int(getattr(self, f.name)) for f in fields(self)))
@@ -99,8 +101,9 @@ class Options:
     def label(self) -> str:
         if self.mode == DPO_MODE_FLAT:
             return "flat"
-        g = {0: "none", 1: "wave", 2: "block", 3: f"{self.agg_blocks}-block"}[self.agg]
-        return f"T{self.threshold}-CF{self.coarsen}-{g}"
+        g = {0: "none", 1: "wave", 2: "block", 3: f"{self.agg_blocks}-block", 4: "grid"}[self.agg]
+        at = f"-A{self.agg_threshold}" if self.agg_threshold else ""
+        return f"T{self.threshold}-CF{self.coarsen}-{g}{at}"
 
 
 _lib = None

@@ -222,3 +222,29 @@ def test_sssp_s21_full_size():
         got, _ = run_sssp(dg, src, o)
         assert np.array_equal(got, want), o.label()
     cert.check_sssp(g, src, got)
+
+
+def test_aggregation_threshold_and_grid_granularity(s14p):
+    """Sec. V-B aggregation threshold at wave and block granularity, and the
+    grid granularity of Sec. II-B: same levels, same thresholding and
+    coarsening counts; an unreachable threshold makes every launch its own
+    grid (descriptors == records)."""
+    g, dg = s14p
+    s = int(gg.sample_sources(g, 1, 5)[0])
+    want, _ = oracle.bfs(g, s)
+    cases = [dpo.Options(threshold=8, coarsen=2, agg=dpo.DPO_AGG_WAVE, agg_threshold=16),
+             dpo.Options(threshold=8, coarsen=2, agg=dpo.DPO_AGG_BLOCK, agg_threshold=64),
+             dpo.Options(threshold=0, coarsen=1, agg=dpo.DPO_AGG_BLOCK, agg_threshold=10**9),
+             dpo.Options(threshold=0, coarsen=4, agg=dpo.DPO_AGG_WAVE, agg_threshold=10**9),
+             dpo.Options(threshold=32, coarsen=2, agg=dpo.DPO_AGG_GRID),
+             dpo.Options(threshold=0, coarsen=1, agg=dpo.DPO_AGG_GRID)]
+    for o in cases:
+        got, st = run_bfs(dg, s, o)
+        assert np.array_equal(got, want), o.label()
+        check_bfs_stats(g, want, o, st)
+        if o.agg_threshold == 10**9:
+            assert st["descriptors"] == st["records"], o.label()
+        if o.agg == dpo.DPO_AGG_GRID:
+            assert st["descriptors"] <= st["levels"], o.label()
+        d, _ = run_sssp(dg, gg.max_degree_vertex(g), o)
+        assert np.array_equal(d, oracle.dijkstra(g, gg.max_degree_vertex(g))), o.label()
