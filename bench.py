@@ -35,7 +35,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="bfs22",
-                   choices=["bfs22", "sssp21", "bfs12", "batch", "serve"])
+                   choices=["bfs22", "sssp21", "bfs12", "batch", "serve", "road"])
     p.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
     p.add_argument("--serve-seconds", type=float, default=0.5)
     p.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
@@ -200,6 +200,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args, dpo, torch, full_line=True)), flush=True)
+        return
+    if args.workload == "road":
+        print(json.dumps(bench_road(args, dpo, torch)), flush=True)
         return
     wl = Workload(args.workload)
     dg = dpo.DeviceGraph.from_host(wl.g)
@@ -467,6 +470,39 @@ def bench_serve(args, dpo, torch, full_line=False):
             "mix": "70% BFS / 30% SSSP", "steps_per_replay": 4, "max_slots": max_slots}
 
 
+# ---------------------------------------------------------------- low nesting
+def bench_road(args, dpo, torch):
+    """Low-nesting control (the paper's road-graph experiment, Sec. VIII-D):
+    a perturbed 514 x 514 grid (264,196 vertices, average degree ~3, maximum
+    8) standing in for USA-road-d.NY.  Flat vs nested with the threshold above
+    the largest degree (every child serialised, no launch) vs nested T=0."""
+    from paper_2201_02789_amd import graphgen as gg
+    g = gg.road_like(514, 514, 3)
+    srcs = gg.sample_sources(g, 4, 1)
+    dg = dpo.DeviceGraph.from_host(g)
+    deg = g.degrees()
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    res = {"graph": {"n": g.n, "m": g.m, "avg_degree": round(float(deg.mean()), 3),
+                     "max_degree": int(deg.max())}}
+    cfgs = {"flat": dpo.Options.flat(),
+            "nested_T_above_max": dpo.Options(threshold=int(deg.max()) + 1, coarsen=1),
+            "nested_T0_4block": dpo.Options(threshold=0, coarsen=1),
+            "naive": dpo.Options.naive()}
+    for name, o in cfgs.items():
+        o.steps_per_replay = 64
+        ws = dpo.alloc_workspace(dg, o)
+        dpo.dpo_bfs(dg, int(srcs[0]), o, out, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in srcs:
+            dpo.dpo_bfs(dg, int(s), o, out, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / len(srcs) * 1e3
+        res[name] = {"ms_per_bfs": round(ms, 3), "options": o.label()}
+        log(f"[road] {name}: {ms:.3f} ms")
+    return {"workload": "road-like grid BFS (low nested parallelism)", **res}
+
+
 def sweep(dpo, torch, wl, dg):
     """Config-2 sweep: T x CF x granularity, plus flat and naive (JSON lines)."""
     import itertools
@@ -475,8 +511,10 @@ def sweep(dpo, torch, wl, dg):
     steps = max(r[2]["levels"] for r in rs) + 1
     grid = [dpo.Options.flat(), dpo.Options.naive()]
     for T, CF, (agg, k) in itertools.product([0, 8, 32, 128, 512], [1, 2, 4, 8],
-                                             [(1, 4), (2, 4), (3, 4), (3, 16)]):
+                                             [(1, 4), (2, 4), (3, 4), (3, 16), (4, 4)]):
         grid.append(dpo.Options(threshold=T, coarsen=CF, agg=agg, agg_blocks=k))
+    for T, agg, at in itertools.product([8, 32], [1, 2], [8, 32]):  # aggregation threshold
+        grid.append(dpo.Options(threshold=T, coarsen=1, agg=agg, agg_threshold=at))
     for o in grid:
         o.steps_per_replay = steps
         pc, _ = measure(dpo, torch, wl, dg, o, 2, 1)
