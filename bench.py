@@ -146,6 +146,35 @@ def reached_stats(dpo, torch, wl, dg, opts):
     return res
 
 
+KERNEL_SOURCES = ["paper_2201_02789_amd/csrc/dpo_kernels.hip",
+                  "paper_2201_02789_amd/csrc/dpo_host.hip",
+                  "paper_2201_02789_amd/csrc/dpo_internal.h"]
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, options_label):
+    """HBM bytes per launch from the committed counter summary
+    (profiles/<workload>_traffic.json: FETCH_SIZE and WRITE_SIZE per traversal,
+    scaled by a plain copy of known size), or None when the kernels changed
+    since the counters were taken or the options differ."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sources_sha256") != kernel_sources_sha() or t.get("options") != options_label:
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
 def algorithmic_bytes(kind, m_r, n_r):
     # BFS: col_idx + level probe per edge, row_ptr pair + level write + frontier
     # write/read per reached vertex.  SSSP: col + weight + dist probe per edge.
@@ -243,8 +272,9 @@ def main():
     achieved = float((bytes_call.sum() / launches.sum()) /
                      ((mean_call_ms.sum() * 1e-3) / launches.sum()) / 1e9)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"step_kernel<{wl.kind.upper()},{opts.label()}>",
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, opts.label()),
+                "kernel": f"level step: parent_kernel + child_kernel <{wl.kind.upper()}, {opts.label()}>",
                 "launches_per_traversal": float(launches.mean()),
                 "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
                 "algorithmic_bytes_per_launch": round(float(bytes_call.sum() / launches.sum()))}
