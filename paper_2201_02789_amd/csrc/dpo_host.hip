@@ -27,8 +27,8 @@ constexpr int kMaxCachedGraphs = 64;
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t state, queries, qlist, qmap, grp_packed, grp_done, front0, front1, visit, rec, rec_q, desc,
-      stats, total;
+  size_t state, queries, qlist, qmap, grp_packed, grp_done, front0, front1, visit, dist2, rec, rec_q,
+      desc, stats, total;
   int32_t ngroups_cap, desc_cap, fcap;
 };
 
@@ -83,7 +83,8 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
   L.front0 = off; off = align_up(off + fslots * 4);
   L.front1 = off; off = align_up(off + fslots * 4);
-  L.visit = off; off = align_up(off + (size_t)slots * 4);
+  L.visit = off; off = align_up(off + (size_t)slots * 4);  // SSSP stamps / two BFS bitmaps
+  L.dist2 = off; off = align_up(off + (size_t)slots * 4);  // SSSP second distance array
   L.rec = off; off = align_up(off + (size_t)slots * 16);
   L.rec_q = off; off = align_up(off + (size_t)slots * 4);
   L.desc = off; off = align_up(off + (size_t)NQD * L.desc_cap * 16);
@@ -286,6 +287,8 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.front0 = (int32_t*)(base + lay.front0);
   a.front1 = (int32_t*)(base + lay.front1);
   a.visit = (uint32_t*)(base + lay.visit);
+  a.dist2 = problem == PROB_SSSP ? (uint32_t*)(base + lay.dist2) : nullptr;
+  a.vwords = (int32_t)cdiv(slots, 32);
   a.rec = (int4*)(base + lay.rec);
   a.rec_q = (int32_t*)(base + lay.rec_q);
   a.qmap = (int32_t*)(base + lay.qmap);

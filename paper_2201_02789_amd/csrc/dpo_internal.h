@@ -57,14 +57,15 @@ struct Args {
   const int32_t* col;
   const uint32_t* w;
   int32_t* level;                  // [slots] BFS output
-  uint32_t* dist;                  // [slots] SSSP output
+  uint32_t* dist;                  // [slots] SSSP output (distance array 0)
+  uint32_t* dist2;                 // [slots] SSSP distance array 1 (equal to dist at the end)
   State* st;
   Query* q;                        // [nq]
   unsigned long long* grp_packed;  // [3][ngroups_cap]: hi32 records, lo32 child blocks
   uint32_t* grp_done;              // [3][ngroups_cap]: blocks of the group finished
   int32_t* front0;                 // [NQF * fcap + slots]
   int32_t* front1;
-  uint32_t* visit;                 // BFS bitmap words / SSSP stamps, indexed by slot
+  uint32_t* visit;                 // BFS: two bitmaps of vwords words; SSSP: stamps [slots]
   int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
   int32_t* rec_q;                  // [slots] query of each record
   int32_t* qmap;                   // [slots / 32] query owning each 32-slot chunk
@@ -81,6 +82,8 @@ struct Args {
   int32_t count_stats;
   int32_t agg_threshold;           // wave / block granularity: fewer launching parents
                                    // than this launch individually (Sec. V-B)
+  int32_t vwords;                  // words of one BFS bitmap (slots / 32)
+  int32_t pad1;
 };
 
 const void* parent_kernel_ptr(int problem, int gran);

@@ -38,9 +38,11 @@
 // coarsened block runs the coarsening loop over CF original blocks of CB lanes
 // (Sec. IV-B) with coalesced col_idx reads.
 //
-// Child body: BFS claims v in a visited bitmap (one bit per output slot,
-// L2-resident) and writes its level; SSSP relaxes dist with atomicMin and
-// queues v once per iteration through an iteration stamp.
+// Child body: BFS probes a visited bitmap (one bit per output slot,
+// L2-resident), claims v in a second bitmap and writes its level; SSSP relaxes
+// a second distance array with atomicMin and queues v once per iteration
+// through an iteration stamp.  The probed and the updated copies swap every
+// level.
 //
 // Queries: a launch may carry many traversals ("queries") over graphs packed
 // in one CSR arena.  Query q owns the output slots [slot0, slot0 + n) (slot0 a
@@ -183,11 +185,38 @@ struct Elem {
   uint32_t du;    // parent distance (SSSP)
 };
 
-// The child body for U neighbours at a time: all probes are issued before any
-// atomic, so the U memory round trips overlap.  BFS claims the slot in the
-// visited bitmap and writes its level; SSSP relaxes dist with atomicMin and
-// queues the slot once per iteration through its stamp.  out[u] = slot to
-// append, or -1.
+// Level L reads one copy of the visited state and updates the other; the two
+// copies swap roles at the next level.  Device atomics on lines that other
+// waves keep probing with plain loads run more than ten times slower on this
+// chip than atomics on lines that only atomics touch, so the probed copy stays
+// read-only for the whole level and the updated copy is only reached by
+// atomics.
+// BFS: bit v of the probed bitmap is set for every vertex discovered before
+// level L; a claim is an atomicOr on the other bitmap.  The claim bitmap lacks
+// exactly the vertices claimed at level L - 1 (the frontier of level L), which
+// the parent kernel folds in during the level.
+__device__ __forceinline__ const uint32_t* probe_bits(const Args& a, uint32_t L) {
+  return a.visit + (size_t)(L & 1) * a.vwords;
+}
+__device__ __forceinline__ uint32_t* claim_bits(const Args& a, uint32_t L) {
+  return a.visit + (size_t)((L + 1) & 1) * a.vwords;
+}
+// SSSP: distances read at level L (complete up to level L - 1) and the array
+// that receives the level's atomicMin (it lacks the improvements of level
+// L - 1, all at frontier vertices of level L, folded in by the parent kernel).
+__device__ __forceinline__ const uint32_t* dist_probe(const Args& a, uint32_t L) {
+  return (L & 1) ? a.dist2 : a.dist;
+}
+__device__ __forceinline__ uint32_t* dist_live(const Args& a, uint32_t L) {
+  return (L & 1) ? a.dist : a.dist2;
+}
+
+// Child body for U neighbours per lane (v < 0: none), all probes issued before
+// any atomic so that the U round trips overlap.  BFS: probe, then claim the
+// unvisited ones and write their level.  SSSP: relax (atomicMin) the edges
+// that improve on the probed distance; an improved vertex joins the next
+// frontier once per level (iteration stamp exchanged atomically).  out[u] is
+// the slot to append to the next frontier, or -1.
 template <int P, int U>
 __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U],
                                             const uint32_t (&w)[U], const Elem (&c)[U],
@@ -204,13 +233,15 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
     out[u] = -1;
   }
   if (P == PROB_BFS) {
+    const uint32_t* pb = probe_bits(a, L);
+    uint32_t* cb = claim_bits(a, L);
     uint32_t word[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? a.visit[(uint32_t)sl[u] >> 5] : ~0u;
+    for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? pb[(uint32_t)sl[u] >> 5] : ~0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t bit = 1u << (sl[u] & 31);
-      if (sl[u] >= 0 && !(word[u] & bit)) word[u] = atomicOr(&a.visit[(uint32_t)sl[u] >> 5], bit);
+      if (sl[u] >= 0 && !(word[u] & bit)) word[u] = atomicOr(&cb[(uint32_t)sl[u] >> 5], bit);
       else word[u] = ~0u;
     }
 #pragma unroll
@@ -221,24 +252,24 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
       }
     }
   } else {
+    const uint32_t* dp = dist_probe(a, L);
+    uint32_t* dl = dist_live(a, L);
     uint32_t nd[U], cur[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       nd[u] = c[u].du + w[u];
-      cur[u] = sl[u] >= 0 ? a.dist[sl[u]] : 0u;
+      cur[u] = sl[u] >= 0 ? dp[sl[u]] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = atomicMin(&a.dist[sl[u]], nd[u]);
+      if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = atomicMin(&dl[sl[u]], nd[u]);
       else cur[u] = 0u;
     }
     const uint32_t it = L + 1;
     uint32_t stamp[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) stamp[u] = nd[u] < cur[u] ? a.visit[sl[u]] : it;
-#pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (nd[u] < cur[u] && stamp[u] != it) stamp[u] = atomicExch(&a.visit[sl[u]], it);
+      if (nd[u] < cur[u]) stamp[u] = atomicExch(&a.visit[sl[u]], it);
       else stamp[u] = it;
     }
 #pragma unroll
@@ -415,7 +446,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         q = (int32_t)p.q;
         launch = deg > 0 && deg >= p.T;
         if (launch) {
-          if (P == PROB_SSSP) du = a.dist[p.slot];
+          if (P == PROB_SSSP) du = dist_probe(a, L)[p.slot];
           // coarsened grid size (Sec. IV-B)
           cg = ceil_div(ceil_div((uint32_t)deg, (uint32_t)a.CB), (uint32_t)p.CF);
         }
@@ -534,6 +565,11 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   }
 
   // ---- pass 2: thresholded children run serially in their parent (Sec. III-B)
+  // The copy updated at this level gets the frontier's own vertices (the
+  // previous level's discoveries / improvements): one atomic per frontier
+  // entry, or, for a BFS frontier with more entries than bitmap words, one per
+  // non-zero word of the probed bitmap.
+  const bool word_fold = P == PROB_BFS && F > (uint32_t)a.vwords;
   for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
     const uint32_t i = vb * PB + tid;
     int32_t start = 0, deg = 0;
@@ -547,10 +583,23 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       atomicOr(&s_live[p.q >> 5], 1u << (p.q & 31));
       const bool ser = deg > 0 && (G == AGG_FLAT || deg < p.T);
       if (!ser) deg = 0;
-      if (P == PROB_SSSP && ser) e.du = a.dist[p.slot];
+      if (P == PROB_SSSP) {
+        e.du = dist_probe(a, L)[p.slot];
+        atomicMin(&dist_live(a, L)[p.slot], e.du);
+      } else if (!word_fold) {
+        atomicOr(&claim_bits(a, L)[(uint32_t)p.slot >> 5], 1u << (p.slot & 31));
+      }
       if (ser) { ++cn.serial; cn.eser += deg; }
     }
     serial_children<P>(a, start, deg, e, L, s, cur, fout, lane);
+  }
+  if (word_fold) {
+    const uint32_t* pb = probe_bits(a, L);
+    uint32_t* cb = claim_bits(a, L);
+    for (uint32_t w = blockIdx.x * PB + tid; w < (uint32_t)a.vwords; w += gridDim.x * PB) {
+      const uint32_t x = pb[w];
+      if (x) atomicOr(&cb[w], x);
+    }
   }
   block_flush(s, a, cur, fout, tid, s_bc);
   // queries with frontier entries at this level are still running
@@ -781,14 +830,20 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
       if (P == PROB_BFS) {
         a.level[s0 + v] = (v == src) ? 0 : -1;
       } else {
-        a.dist[s0 + v] = (v == src) ? 0u : 0xFFFFFFFFu;
+        const uint32_t d = (v == src) ? 0u : 0xFFFFFFFFu;
+        a.dist[s0 + v] = d;
+        a.dist2[s0 + v] = d;
         a.visit[s0 + v] = 0u;
       }
     }
     const uint32_t words = ((uint32_t)Q.n + 31) / 32;
     for (uint32_t i = gid; i < words; i += gsz) {
       a.qmap[s0 / 32 + i] = qi;
-      if (P == PROB_BFS) a.visit[s0 / 32 + i] = (i == src >> 5) ? (1u << (src & 31)) : 0u;
+      if (P == PROB_BFS) {
+        const uint32_t x = (i == src >> 5) ? (1u << (src & 31)) : 0u;
+        a.visit[s0 / 32 + i] = x;  // both bitmaps hold the source
+        a.visit[(size_t)a.vwords + s0 / 32 + i] = x;
+      }
     }
   }
   if (reset) {
