@@ -190,11 +190,16 @@ struct Elem {
 // waves keep probing with plain loads run more than ten times slower on this
 // chip than atomics on lines that only atomics touch, so the probed copy stays
 // read-only for the whole level and the updated copy is only reached by
-// atomics.
+// atomics and by agent-coherent loads (which do not slow them down).  Those
+// loads filter the candidates that the probed copy, frozen at the start of the
+// level, cannot: vertices already found during the level.
 // BFS: bit v of the probed bitmap is set for every vertex discovered before
 // level L; a claim is an atomicOr on the other bitmap.  The claim bitmap lacks
 // exactly the vertices claimed at level L - 1 (the frontier of level L), which
 // the parent kernel folds in during the level.
+__device__ __forceinline__ uint32_t coherent_load(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ const uint32_t* probe_bits(const Args& a, uint32_t L) {
   return a.visit + (size_t)(L & 1) * a.vwords;
 }
@@ -238,6 +243,12 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
     uint32_t word[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? pb[(uint32_t)sl[u] >> 5] : ~0u;
+    // vertices found earlier in this level are still clear in the probed
+    // bitmap: a coherent load of the claim word skips their atomics
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31))))
+        word[u] = coherent_load(&cb[(uint32_t)sl[u] >> 5]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t bit = 1u << (sl[u] & 31);
@@ -261,6 +272,9 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
       cur[u] = sl[u] >= 0 ? dp[sl[u]] : 0u;
     }
 #pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = coherent_load(&dl[sl[u]]);
+#pragma unroll
     for (int u = 0; u < U; ++u) {
       if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = atomicMin(&dl[sl[u]], nd[u]);
       else cur[u] = 0u;
@@ -268,8 +282,10 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
     const uint32_t it = L + 1;
     uint32_t stamp[U];
 #pragma unroll
+    for (int u = 0; u < U; ++u) stamp[u] = nd[u] < cur[u] ? coherent_load(&a.visit[sl[u]]) : it;
+#pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (nd[u] < cur[u]) stamp[u] = atomicExch(&a.visit[sl[u]], it);
+      if (nd[u] < cur[u] && stamp[u] != it) stamp[u] = atomicExch(&a.visit[sl[u]], it);
       else stamp[u] = it;
     }
 #pragma unroll
@@ -626,36 +642,72 @@ __device__ __forceinline__ uint32_t wave_upper_search(uint32_t n, uint32_t t, in
   return lo;
 }
 
-// Lane i of a wave holds record r0 + i of the current descriptor and the
-// fields of its query, so consecutive small records cost one wave-wide load.
+// Lane k of a wave holds record r0 + k of the current descriptor, the fields
+// of its query and its share of the wave's child blocks [t0, t1): blocks
+// [lo, hi) of its coarsened grid, i.e. the edges [elo, ehi) of its row, cut
+// into 64-lane slices.  Consecutive small records cost one wave-wide load.
 struct Window {
-  int4 rec;      // {row start, deg, offset, parent distance}
-  int32_t CF, vbase, n, sbase, lv;
+  int32_t rs, elo, ehi;             // row start, edge range of the share
+  uint32_t excl, nslices;           // exclusive scan of the slice counts, total
+  int32_t vbase, n, sbase, lv;      // query fields (Elem)
+  uint32_t du;
+  bool last;                        // the wave's range ends in this window
+  bool bad;
 };
 
-__device__ __forceinline__ Window load_window(const Args& a, uint32_t base, uint32_t wn, int lane,
-                                              uint32_t L) {
-  Window w{make_int4(0, 0, 0, 0), 1, 0, 0, 0, 0};
+__device__ __forceinline__ Window load_window(const Args& a, uint32_t base, uint32_t wn,
+                                              uint32_t gbase, uint32_t t0, uint32_t t1, int lane,
+                                              uint32_t L, uint32_t& blocks, uint32_t& edges) {
+  Window w{0, 0, 0, 0u, 0u, 0, 0, 0, 0, 0u, false, false};
+  uint32_t ns = 0;
+  bool bad = false, ends = false;
   if ((uint32_t)lane < wn) {
-    w.rec = a.rec[base + lane];
+    const int4 rec = a.rec[base + lane];
     const int32_t q = a.rec_q[base + lane];
+    int32_t CF = 1;
     if ((uint32_t)q < (uint32_t)a.nq) {
       const Query Q = a.q[q];
-      w.CF = Q.CF;
+      CF = max(Q.CF, 1);
       w.vbase = Q.vbase;
       w.n = Q.n;
       w.sbase = Q.slot0 - Q.vbase;
       w.lv = (int32_t)(L + 1) - Q.lstart;
     } else {
-      w.rec.y = 0;  // flagged below as a bad record
+      bad = true;
+    }
+    const int32_t deg = rec.y;
+    if (deg <= 0 || rec.x < 0 || (int64_t)rec.x + deg > (int64_t)a.m) bad = true;
+    if (!bad) {
+      // coarsened grid of the record (Sec. IV-B): ceil(ceil(deg / CB) / CF)
+      // blocks of CF * CB edges, starting at global block G
+      const uint32_t span = (uint32_t)CF * (uint32_t)a.CB;
+      const uint32_t cgr = ceil_div((uint32_t)deg, span);
+      const uint32_t G = gbase + (uint32_t)rec.z;
+      const uint32_t lo = max(G, t0), hi = min(G + cgr, t1);
+      ends = G + cgr >= t1;
+      if (hi > lo) {
+        w.rs = rec.x;
+        w.elo = (int32_t)((lo - G) * span);
+        w.ehi = min(deg, (int32_t)((hi - G) * span));
+        ns = ceil_div((uint32_t)(w.ehi - w.elo), 64u);
+        blocks += hi - lo;
+        edges += (uint32_t)(w.ehi - w.elo);
+      }
+      w.du = (uint32_t)rec.w;
     }
   }
+  const uint32_t incl = wave_incl_scan(ns, lane);
+  w.excl = incl - ns;
+  w.nslices = __shfl(incl, 63, 64);
+  w.last = __any(ends);
+  w.bad = __any(bad);
   return w;
 }
 
-// One wave runs one coarsened child block at a time: the wave's share of the
-// aggregated blocks is contiguous, so the first block is disaggregated by
-// search and the following ones by advancing along the scanned offsets.
+// One wave runs a contiguous share [t0, t1) of the level's aggregated child
+// blocks: the parent of its first block is found by search (the
+// disaggregation of Sec. V-A), then records are taken 64 at a time and their
+// slices U at a time.
 template <int P>
 __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
@@ -690,7 +742,6 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   const uint32_t t1 = (uint32_t)((uint64_t)(gw + 1) * B / nwaves);
   Counters cn{0, 0, 0, 0, 0, 0, 0};
   Stage s{s_stage[wave], 0u};
-  const uint32_t CB = (uint32_t)a.CB;
 
   if (t0 < t1) {
     // disaggregation of the first block (Sec. V-A): queue, descriptor, record
@@ -700,96 +751,69 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
     const uint32_t tq = t0 - s_qpre[q];
     uint32_t d = wave_upper_search(s_qnd[q], tq, lane, [&](uint32_t p) { return (uint32_t)dq[p].z; });
     int4 dd = dq[d];
-    const uint32_t tr = tq - (uint32_t)dd.z;
-    uint32_t r = wave_upper_search((uint32_t)dd.y, tr, lane,
+    uint32_t r = wave_upper_search((uint32_t)dd.y, tq - (uint32_t)dd.z, lane,
                                    [&](uint32_t p) { return (uint32_t)a.rec[dd.x + p].z; });
-    uint32_t j = tr - (uint32_t)a.rec[dd.x + r].z;
-
-    uint32_t r0 = r, wn = min(64u, (uint32_t)dd.y - r0);
-    Window win = load_window(a, (uint32_t)dd.x + r0, wn, lane, L);
-    uint32_t slice = 0;  // next 64-lane slice of block j of record r
-    uint32_t t = t0;     // child block being sliced
     constexpr int U = 8;
-    bool bad = false;
-    while (t < t1 && !bad) {
-      // Fill U slots with 64-lane slices of consecutive aggregated child blocks.
-      // Coarsening loop (Sec. IV-B): block j of a record covers original
-      // blocks j*CF .. j*CF+CF-1 of CB lanes, i.e. the contiguous edge range
-      // [j*CF*CB, (j+1)*CF*CB), taken here 64 lanes at a time.
-      int32_t e0[U], cnt[U];
-      Elem c[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        e0[u] = 0;
-        cnt[u] = 0;
-        c[u] = Elem{0, 0, 0, 0, 0u};
-        if (t < t1 && !bad && r - r0 < wn) {
-          const uint32_t wi = r - r0;
-          const int32_t start = __builtin_amdgcn_readlane(win.rec.x, wi);
-          const int32_t deg = __builtin_amdgcn_readlane(win.rec.y, wi);
-          const int32_t CF = __builtin_amdgcn_readlane(win.CF, wi);
-          const uint32_t cgr = ceil_div(ceil_div((uint32_t)deg, CB), (uint32_t)max(CF, 1));
-          if (deg <= 0 || start < 0 || (int64_t)start + deg > (int64_t)a.m || j >= cgr) {
-            bad = true;
-          } else {
-            const int32_t base_idx = (int32_t)(j * (uint32_t)CF * CB);
-            const int32_t blim = min(deg - base_idx, CF * (int32_t)CB);
-            const int32_t off = (int32_t)slice * 64;
-            e0[u] = start + base_idx + off;
-            cnt[u] = min(64, blim - off);
-            c[u].vbase = __builtin_amdgcn_readlane(win.vbase, wi);
-            c[u].n = __builtin_amdgcn_readlane(win.n, wi);
-            c[u].sbase = __builtin_amdgcn_readlane(win.sbase, wi);
-            c[u].lv = __builtin_amdgcn_readlane(win.lv, wi);
-            c[u].du = (uint32_t)__builtin_amdgcn_readlane(win.rec.w, wi);
-            if (off + 64 >= blim) {  // block done
-              slice = 0;
-              ++t;
-              if (lane == 0) ++cn.child;
-              if (++j == cgr) {
-                j = 0;
-                ++r;
-              }
-            } else {
-              ++slice;
-            }
-          }
-        }
-      }
-      if (bad) {
+    while (true) {
+      const uint32_t wn = min(64u, (uint32_t)dd.y - r);
+      const Window win = load_window(a, (uint32_t)dd.x + r, wn, s_qpre[q] + (uint32_t)dd.z, t0, t1,
+                                     lane, L, cn.child, cn.echild);
+      if (win.bad) {
         if (lane == 0) set_error(st, ERR_CAPACITY);
         break;
       }
-      int32_t v[U], out[U];
-      uint32_t w[U];
+      // Coarsening loop (Sec. IV-B): a coarsened block covers original blocks
+      // j*CF .. j*CF+CF-1 of CB lanes, the contiguous edges [j*CF*CB,
+      // (j+1)*CF*CB) of its row, taken here 64 lanes at a time.
+      for (uint32_t x0 = 0; x0 < win.nslices; x0 += U) {
+        int32_t v[U], out[U];
+        uint32_t w[U];
+        Elem c[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const bool on = lane < cnt[u];
-        v[u] = on ? a.col[e0[u] + lane] : -1;
-        w[u] = (P == PROB_SSSP && on) ? a.w[e0[u] + lane] : 0u;
-        if (on) ++cn.echild;
-      }
-      visit_batch<P, U>(a, v, w, c, L, out);
-#pragma unroll
-      for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
-      // refill the record window when it is used up
-      if (t < t1 && r - r0 >= wn) {
-        if (r >= (uint32_t)dd.y) {  // next descriptor (next queue if need be)
-          r = 0;
-          if (++d >= s_qnd[q]) {
-            d = 0;
-            do { ++q; } while (q < NQD && s_qnd[q] == 0);
-            if (q >= NQD) {
-              if (lane == 0) set_error(st, ERR_CAPACITY);
-              break;
+        for (int u = 0; u < U; ++u) {
+          v[u] = -1;
+          w[u] = 0u;
+          c[u] = Elem{0, 0, 0, 0, 0u};
+          const uint32_t x = x0 + u;
+          if (x < win.nslices) {
+            // record of slice x: the last lane whose scan start is <= x
+            const uint32_t k =
+                (uint32_t)__popcll(__ballot((uint32_t)lane < wn && win.excl <= x)) - 1u;
+            const int32_t rs = __builtin_amdgcn_readlane(win.rs, k);
+            const int32_t e0 = rs + __builtin_amdgcn_readlane(win.elo, k) +
+                               (int32_t)((x - (uint32_t)__builtin_amdgcn_readlane((int32_t)win.excl, k)) * 64u);
+            const int32_t e1 = rs + __builtin_amdgcn_readlane(win.ehi, k);
+            c[u].vbase = __builtin_amdgcn_readlane(win.vbase, k);
+            c[u].n = __builtin_amdgcn_readlane(win.n, k);
+            c[u].sbase = __builtin_amdgcn_readlane(win.sbase, k);
+            c[u].lv = __builtin_amdgcn_readlane(win.lv, k);
+            c[u].du = (uint32_t)__builtin_amdgcn_readlane((int32_t)win.du, k);
+            if (e0 + lane < e1) {
+              v[u] = a.col[e0 + lane];
+              if (P == PROB_SSSP) w[u] = a.w[e0 + lane];
             }
-            dq = a.desc + (size_t)q * a.desc_cap;
           }
-          dd = dq[d];
         }
-        r0 = r;
-        wn = min(64u, (uint32_t)dd.y - r0);
-        win = load_window(a, (uint32_t)dd.x + r0, wn, lane, L);
+        visit_batch<P, U>(a, v, w, c, L, out);
+#pragma unroll
+        for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
+      }
+      if (win.last) break;
+      // next window: rest of this descriptor, else the next one (next queue
+      // if need be)
+      r += wn;
+      if (r >= (uint32_t)dd.y) {
+        r = 0;
+        if (++d >= s_qnd[q]) {
+          d = 0;
+          do { ++q; } while (q < NQD && s_qnd[q] == 0);
+          if (q >= NQD) {
+            if (lane == 0) set_error(st, ERR_CAPACITY);
+            break;
+          }
+          dq = a.desc + (size_t)q * a.desc_cap;
+        }
+        dd = dq[d];
       }
     }
   }
