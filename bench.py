@@ -48,6 +48,10 @@ def parse():
     p.add_argument("--cpu-sources", type=int, default=4)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 512 MiB device copy (counter calibration)")
+    p.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                   help="write profiles/<workload>_kernels.md and _traffic.json from the "
+                        "rocprofv3 CSV output under DIR (trace/, fetch/, write/, "
+                        "copy_fetch/, copy_write/; trace/out.json = the traced bench line)")
     return p.parse_args()
 
 
@@ -202,8 +206,104 @@ def cpu_baseline(wl, nsrc):
                       f"single thread, {dt:.1f} s"}
 
 
+# ---------------------------------------------------------------- profiles
+COPY_BYTES = 512 << 20  # --calibrate-copy: bytes read and written per copy
+COPY_REPS = 3
+
+
+def _csv(dirpath, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(dirpath, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {dirpath}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("dpo::", "")
+
+
+def summarize_profiles(args, d):
+    """Level-step kernel time from a kernel trace and HBM bytes from FETCH_SIZE
+    / WRITE_SIZE counter runs, each counter scaled by what it reads for a plain
+    copy of known size."""
+    with open(os.path.join(d, "trace", "out.json")) as f:
+        line = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    label, launches_per = line["config"]["options"], line["roofline"]["launches_per_traversal"]
+    step = ("parent_kernel", "child_kernel")
+
+    trace = _csv(os.path.join(d, "trace"), "kernel_trace.csv")
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"])) for r in trace]
+    stats = {}
+    for t0, t1, n in rows:
+        c, tot = stats.get(n, (0, 0))
+        stats[n] = (c + 1, tot + (t1 - t0))
+    traversals = sum(1 for _, _, n in rows if n == "init_kernel")
+    step_ns = sum(t1 - t0 for t0, t1, n in rows if n.startswith(step))
+    launches = traversals * launches_per
+    kernel_us = step_ns / launches / 1e3
+
+    def per_dispatch(sub, counter):
+        return [(_short(r["Kernel_Name"]), float(r["Counter_Value"]))
+                for r in _csv(os.path.join(d, sub), "counter_collection.csv")
+                if r["Counter_Name"] == counter]
+
+    def copy_scale(sub, counter):
+        # every dispatch of the device copies (however the runtime splits them)
+        vals = [v for n, v in per_dispatch(sub, counter) if "copy" in n.lower()]
+        return COPY_REPS * COPY_BYTES / (sum(vals) * 1024)
+
+    sf, sw = copy_scale("copy_fetch", "FETCH_SIZE"), copy_scale("copy_write", "WRITE_SIZE")
+    fetch = [(n, v) for n, v in per_dispatch("fetch", "FETCH_SIZE") if n.startswith(step)]
+    write = [(n, v) for n, v in per_dispatch("write", "WRITE_SIZE") if n.startswith(step)]
+    trav_pmc = sum(1 for n, _ in per_dispatch("fetch", "FETCH_SIZE") if n == "init_kernel")
+    launches_pmc = trav_pmc * launches_per
+    fetch_b = sum(v for _, v in fetch) * 1024 * sf / launches_pmc
+    write_b = sum(v for _, v in write) * 1024 * sw / launches_pmc
+    traffic = {"workload": args.workload, "options": label,
+               "kernel_sources_sha256": kernel_sources_sha(),
+               "hbm_bytes_per_launch": round(fetch_b + write_b),
+               "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
+               "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
+               "traversals": trav_pmc, "launches_per_traversal": launches_per}
+    out_json = os.path.join(ROOT, "profiles", f"{args.workload}_traffic.json")
+    with open(out_json, "w") as f:
+        json.dump(traffic, f, indent=1)
+        f.write("\n")
+
+    alg = line["roofline"]["algorithmic_bytes_per_launch"]
+    top = sorted(stats.items(), key=lambda kv: -kv[1][1])[:8]
+    md = [f"# {args.workload}: kernel time and HBM traffic ({label})", "",
+          "Commands (repository root, MI355X, `cd /tmp && export TMPDIR=/tmp` first):", "",
+          "```"] + [ln.rstrip() for ln in open(os.path.join(d, "commands.txt"))] + ["```", "",
+          "## Kernel trace (`rocprofv3 --kernel-trace --stats`)", "",
+          "| kernel | calls | total ms | mean us |", "|---|---|---|---|"]
+    md += [f"| {n} | {c} | {t / 1e6:.3f} | {t / c / 1e3:.2f} |" for n, (c, t) in top]
+    md += ["", f"Traversals traced: {traversals}; level-step launches per traversal "
+               f"{launches_per:.4g} (levels + 1).",
+           f"Level step (parent_kernel + child_kernel) kernel time per launch: **{kernel_us:.2f} us** "
+           f"(bench line of the traced run: mean_launch_us {line['roofline']['mean_launch_us']}, "
+           f"which also holds the gaps between graph nodes).", "",
+           "## HBM traffic (`rocprofv3 --pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`)", "",
+           f"Copy calibration (`bench.py --calibrate-copy`, {COPY_BYTES >> 20} MiB read + written): "
+           f"bytes = counter KiB x 1024 x {sf:.4f} (fetch), x {sw:.4f} (write).", "",
+           f"Per level-step launch over {trav_pmc} traversals: fetch {fetch_b / 1e6:.2f} MB, "
+           f"write {write_b / 1e6:.2f} MB, total **{(fetch_b + write_b) / 1e6:.2f} MB** "
+           f"vs algorithmic {alg / 1e6:.2f} MB ({(fetch_b + write_b) / alg:.2f}x).", "",
+           f"kernel_sources_sha256 `{traffic['kernel_sources_sha256']}`", ""]
+    out_md = os.path.join(ROOT, "profiles", f"{args.workload}_kernels.md")
+    with open(out_md, "w") as f:
+        f.write("\n".join(md))
+    print(json.dumps({"wrote": [out_md, out_json], "kernel_us_per_launch": round(kernel_us, 2),
+                      "traffic": traffic}))
+
+
 def main():
     args = parse()
+    if args.summarize_profiles:
+        return summarize_profiles(args, args.summarize_profiles)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "independent traversals shard by graph across GPUs, see DESIGN.md", file=sys.stderr)
@@ -214,13 +314,13 @@ def main():
     if args.calibrate_copy:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
         # the scale between those counters and bytes
-        n = (512 << 20) // 4
+        n = COPY_BYTES // 4
         src = torch.ones(n, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
+        for _ in range(COPY_REPS):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": COPY_REPS}))
         return
     dpo.lib()  # fail loudly if the HIP library is missing
 
