@@ -68,6 +68,8 @@ struct Args {
   uint32_t* visit;                 // BFS: two bitmaps of vwords words; SSSP: stamps [slots]
   int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
   int32_t* rec_q;                  // [slots] query of each record
+  int4* ser;                       // [slots rounded up to PB] thresholded parents
+                                   // {row start, deg, slot, parent distance}
   int32_t* qmap;                   // [slots / 32] query owning each 32-slot chunk
   int4* desc;                      // [NQD][desc_cap] {record base, records, block base, -}
   unsigned long long* stats;       // [MAX_GRID][NSTAT], one row per workgroup

@@ -393,9 +393,10 @@ __device__ __forceinline__ Parent load_parent(const Args& a, const int32_t* fin,
 }
 
 // ------------------------------------------------------------ parent kernel
-// Pass 1 decides each parent (threshold), aggregates the launching ones and
-// writes their records (block barriers); pass 2 runs the thresholded parents'
-// serial children with no barrier, so waves do not wait on each other.
+// Pass 1 reads each frontier entry once, decides it (threshold), aggregates
+// the launching ones and writes their records (block barriers) and lists the
+// thresholded ones; pass 2 runs the listed parents' serial children with no
+// barrier, so waves do not wait on each other.
 template <int P, int G>
 __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
@@ -404,6 +405,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ uint32_t s_bc[NW + 8];
   __shared__ unsigned long long s_stats[NSTAT];
   __shared__ uint32_t s_live[MAX_QUERIES / 32];  // queries seen at this level
+  __shared__ uint32_t s_ser[2];                  // serial list: length, next entry
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
@@ -447,26 +449,61 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   Stage s{s_stage[wave], 0u};
   Counters cn{0, 0, 0, 0, 0, 0, 0};
   const uint32_t nvb = ceil_div(F, PB);
+  if (tid == 0) s_ser[0] = 0;  // thresholded parents listed by this workgroup
+  __syncthreads();
 
-  // ---- pass 1: threshold, coarsened grid size, aggregation, launch records
-  if (G != AGG_FLAT) {
-    for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-      const uint32_t i = vb * PB + tid;
-      int32_t start = 0, deg = 0, q = 0;
-      uint32_t du = 0, cg = 0;
-      bool launch = false;
-      if (i < F) {
-        const Parent p = load_parent<P>(a, fin, s_fpre, i, L);
-        start = p.start;
-        deg = p.deg;
-        q = (int32_t)p.q;
-        launch = deg > 0 && deg >= p.T;
-        if (launch) {
-          if (P == PROB_SSSP) du = dist_probe(a, L)[p.slot];
-          // coarsened grid size (Sec. IV-B)
-          cg = ceil_div(ceil_div((uint32_t)deg, (uint32_t)a.CB), (uint32_t)p.CF);
-        }
+  // The copy updated at this level gets the frontier's own vertices (the
+  // previous level's discoveries / improvements): one atomic per frontier
+  // entry, or, for a BFS frontier with more entries than bitmap words, one per
+  // non-zero word of the probed bitmap.
+  const bool word_fold = P == PROB_BFS && F > (uint32_t)a.vwords;
+
+  // ---- pass 1: every frontier entry once.  Threshold, coarsened grid size,
+  // aggregation and launch records; thresholded parents go to this
+  // workgroup's serial list for pass 2.
+  for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const uint32_t i = vb * PB + tid;
+    int32_t start = 0, deg = 0, q = 0, slot = 0;
+    uint32_t du = 0, cg = 0;
+    bool launch = false, ser = false;
+    if (i < F) {
+      const Parent p = load_parent<P>(a, fin, s_fpre, i, L);
+      start = p.start;
+      deg = p.deg;
+      q = (int32_t)p.q;
+      slot = p.slot;
+      ++cn.front;
+      atomicOr(&s_live[p.q >> 5], 1u << (p.q & 31));
+      if (P == PROB_SSSP) {
+        du = dist_probe(a, L)[slot];
+        atomicMin(&dist_live(a, L)[slot], du);
+      } else if (!word_fold) {
+        atomicOr(&claim_bits(a, L)[(uint32_t)slot >> 5], 1u << (slot & 31));
       }
+      launch = G != AGG_FLAT && deg > 0 && deg >= p.T;
+      ser = deg > 0 && !launch;
+      if (launch) {
+        // coarsened grid size (Sec. IV-B)
+        cg = ceil_div(ceil_div((uint32_t)deg, (uint32_t)a.CB), (uint32_t)p.CF);
+      }
+      if (ser) {
+        ++cn.serial;
+        cn.eser += deg;
+      }
+    }
+    {
+      // entry k of the list sits in this workgroup's own virtual blocks
+      const unsigned long long m = __ballot(ser);
+      uint32_t base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_ser[0], (uint32_t)__popcll(m));
+      base = __shfl(base, 0, 64);
+      if (ser) {
+        const uint32_t k = base + lane_rank(m);
+        a.ser[(size_t)(blockIdx.x + (k / PB) * gridDim.x) * PB + k % PB] =
+            make_int4(start, deg, slot, (int32_t)du);
+      }
+    }
+    if (G != AGG_FLAT) {
       if (launch) ++cn.rec;
 
       if (G == AGG_NONE) {
@@ -580,34 +617,54 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     }
   }
 
-  // ---- pass 2: thresholded children run serially in their parent (Sec. III-B)
-  // The copy updated at this level gets the frontier's own vertices (the
-  // previous level's discoveries / improvements): one atomic per frontier
-  // entry, or, for a BFS frontier with more entries than bitmap words, one per
-  // non-zero word of the probed bitmap.
-  const bool word_fold = P == PROB_BFS && F > (uint32_t)a.vwords;
-  for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-    const uint32_t i = vb * PB + tid;
-    int32_t start = 0, deg = 0;
-    Elem e{0, 0, 0, 0, 0u};
-    if (i < F) {
-      Parent p = load_parent<P>(a, fin, s_fpre, i, L);
-      start = p.start;
-      deg = p.deg;
-      e = p.e;
-      ++cn.front;
-      atomicOr(&s_live[p.q >> 5], 1u << (p.q & 31));
-      const bool ser = deg > 0 && (G == AGG_FLAT || deg < p.T);
-      if (!ser) deg = 0;
-      if (P == PROB_SSSP) {
-        e.du = dist_probe(a, L)[p.slot];
-        atomicMin(&dist_live(a, L)[p.slot], e.du);
-      } else if (!word_fold) {
-        atomicOr(&claim_bits(a, L)[(uint32_t)p.slot >> 5], 1u << (p.slot & 31));
+  // ---- pass 2: thresholded children run serially, each by one lane
+  // (Sec. III-B).  A lane whose child is done takes the next parent of the
+  // list, so lanes do not idle until the wave's largest child finishes.
+  __syncthreads();
+  {
+    const uint32_t nser = s_ser[0];
+    if (tid == 0) s_ser[1] = 0;  // next list entry
+    __syncthreads();
+    constexpr int U = 8;
+    int32_t e = 0, end = 0;
+    Elem ctx{0, 0, 0, 0, 0u};
+    while (true) {
+      const bool idle = e >= end;
+      const unsigned long long m = __ballot(idle);
+      uint32_t base = 0;
+      if (m) {
+        if (lane == __builtin_ctzll(m)) base = atomicAdd(&s_ser[1], (uint32_t)__popcll(m));
+        base = __shfl(base, __builtin_ctzll(m), 64);
       }
-      if (ser) { ++cn.serial; cn.eser += deg; }
+      if (idle) {
+        const uint32_t k = base + lane_rank(m);
+        if (k < nser) {
+          const int4 r = a.ser[(size_t)(blockIdx.x + (k / PB) * gridDim.x) * PB + k % PB];
+          const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
+          e = r.x;
+          end = r.x + r.y;
+          ctx.vbase = Q.vbase;
+          ctx.n = Q.n;
+          ctx.sbase = Q.slot0 - Q.vbase;
+          ctx.lv = (int32_t)(L + 1) - Q.lstart;
+          ctx.du = (uint32_t)r.w;
+        }
+      }
+      if (!__any(e < end)) break;
+      int32_t v[U], out[U];
+      uint32_t w[U];
+      Elem c[U];
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        v[r] = (e + r < end) ? a.col[e + r] : -1;
+        w[r] = (P == PROB_SSSP && e + r < end) ? a.w[e + r] : 0u;
+        c[r] = ctx;
+      }
+      visit_batch<P, U>(a, v, w, c, L, out);
+#pragma unroll
+      for (int r = 0; r < U; ++r) stage_push(s, out[r] >= 0, out[r], a, cur, fout, lane);
+      e = min(e + U, end);
     }
-    serial_children<P>(a, start, deg, e, L, s, cur, fout, lane);
   }
   if (word_fold) {
     const uint32_t* pb = probe_bits(a, L);
