@@ -85,6 +85,11 @@ typedef struct {
                                granularity only: when fewer than this many parents
                                of the wave / block launch, each launches its own
                                grid instead of joining an aggregated one; 0 = off */
+  int32_t split_min;        /* >= 0.  A level whose frontier has at least this
+                               many entries probes one copy of the visited state
+                               and sends its atomics to a second copy; narrower
+                               levels use one copy.  Affects speed only.  Default
+                               65536; 0 = always two copies.                      */
 } dpo_options;
 
 typedef struct {

@@ -13,6 +13,8 @@ constexpr int NQF = 64;          // frontier queues (queue = workgroup % 64), pl
 constexpr int MAX_GRID = 4096;   // persistent grid cap (rows of the per-workgroup counters)
 constexpr int NSTAT = 8;
 constexpr int MAX_QUERIES = 4096;  // per-query tables are staged in LDS
+constexpr int PRECHECK_MIN = 32;   // claim candidates per 512-lane batch above which
+                                   // a coherent load precedes the atomics
 
 enum { PROB_BFS = 0, PROB_SSSP = 1 };
 enum { AGG_NONE = 0, AGG_WAVE = 1, AGG_BLOCK = 2, AGG_MULTI = 3, AGG_FLAT = 4 };
@@ -24,7 +26,9 @@ enum { S_FRONT = 0, S_SERIAL, S_REC, S_CHILD, S_ESER, S_ECHILD, S_DESC };
 // kernel of level L can clear the set of level L + 1 while nobody uses it.
 struct LevelSet {
   uint32_t fcnt[NQF + 1];              // next-frontier queue fills (+ overflow)
-  uint32_t pad0[15];
+  uint32_t vmode;                      // visited copies of this level: bit 0 probed
+                                       // buffer, bit 1 split (claims in the other one)
+  uint32_t pad0[14];
   unsigned long long qctr[NQD];        // descriptor queues: hi32 count, lo32 child blocks
 };
 
@@ -33,7 +37,9 @@ struct State {
   uint32_t done;        // set when a level starts with an empty frontier
   uint32_t error;       // first device error code, 0 = none
   uint32_t levels_run;  // index of the last non-empty level + 1
-  uint32_t pad[60];
+  uint32_t vsel[2];     // probed visited buffer of levels with parity 0 / 1
+  uint32_t vstale[2];   // BFS: the other bitmap missed folds (a one-copy level ran)
+  uint32_t pad[56];
   LevelSet set[3];
 };
 
@@ -85,7 +91,8 @@ struct Args {
   int32_t agg_threshold;           // wave / block granularity: fewer launching parents
                                    // than this launch individually (Sec. V-B)
   int32_t vwords;                  // words of one BFS bitmap (slots / 32)
-  int32_t pad1;
+  int32_t split_min;               // frontier size from which a level probes one
+                                   // visited copy and updates the other
 };
 
 const void* parent_kernel_ptr(int problem, int gran);

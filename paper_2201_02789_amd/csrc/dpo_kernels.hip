@@ -185,35 +185,40 @@ struct Elem {
   uint32_t du;    // parent distance (SSSP)
 };
 
-// Level L reads one copy of the visited state and updates the other; the two
-// copies swap roles at the next level.  Device atomics on lines that other
-// waves keep probing with plain loads run more than ten times slower on this
-// chip than atomics on lines that only atomics touch, so the probed copy stays
-// read-only for the whole level and the updated copy is only reached by
-// atomics and by agent-coherent loads (which do not slow them down).  Those
-// loads filter the candidates that the probed copy, frozen at the start of the
-// level, cannot: vertices already found during the level.
-// BFS: bit v of the probed bitmap is set for every vertex discovered before
-// level L; a claim is an atomicOr on the other bitmap.  The claim bitmap lacks
-// exactly the vertices claimed at level L - 1 (the frontier of level L), which
-// the parent kernel folds in during the level.
+// Visited state in two copies.  Device atomics on lines that other waves keep
+// probing with plain loads run more than ten times slower on this chip than
+// atomics on lines that only atomics touch.  So a level with a wide frontier
+// probes one copy, read-only for the whole level, and sends its atomics to the
+// other ("split"); the copies swap at the next level.  A level with a narrow
+// frontier probes and updates one copy, which keeps the atomic next to the
+// probed line and the level short.  At the start of a level the probed copy is
+// complete.  A split level folds its frontier's own vertices (the previous
+// level's discoveries / improvements) into the copy it updates, which then
+// lacks exactly those; SSSP folds at every level, so the unprobed array always
+// lacks just the frontier's improvements.  A one-copy BFS level skips the fold
+// and marks the other bitmap stale (it only ever holds visited vertices); the
+// next split level then folds every non-zero word of the probed bitmap.
+// BFS: buffer i is the bitmap visit + i * vwords.  SSSP: buffer 0 is the
+// output distance array, buffer 1 the workspace one; both hold the result at
+// the end (the last level improves nothing, so its fold leaves them equal).
+struct Vis {
+  const uint32_t* probe;  // read with plain loads
+  uint32_t* claim;        // the level's claims / atomicMin
+  uint32_t* fold;         // receives the frontier's vertices / distances
+  bool split;
+};
+
+template <int P>
+__device__ __forceinline__ Vis vis_of(const Args& a, uint32_t c, bool split) {
+  uint32_t* b0 = P == PROB_BFS ? a.visit : a.dist;
+  uint32_t* b1 = P == PROB_BFS ? a.visit + a.vwords : a.dist2;
+  uint32_t* pb = c ? b1 : b0;
+  uint32_t* ob = c ? b0 : b1;
+  return Vis{pb, split ? ob : pb, ob, split};
+}
+
 __device__ __forceinline__ uint32_t coherent_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ const uint32_t* probe_bits(const Args& a, uint32_t L) {
-  return a.visit + (size_t)(L & 1) * a.vwords;
-}
-__device__ __forceinline__ uint32_t* claim_bits(const Args& a, uint32_t L) {
-  return a.visit + (size_t)((L + 1) & 1) * a.vwords;
-}
-// SSSP: distances read at level L (complete up to level L - 1) and the array
-// that receives the level's atomicMin (it lacks the improvements of level
-// L - 1, all at frontier vertices of level L, folded in by the parent kernel).
-__device__ __forceinline__ const uint32_t* dist_probe(const Args& a, uint32_t L) {
-  return (L & 1) ? a.dist2 : a.dist;
-}
-__device__ __forceinline__ uint32_t* dist_live(const Args& a, uint32_t L) {
-  return (L & 1) ? a.dist : a.dist2;
 }
 
 // Child body for U neighbours per lane (v < 0: none), all probes issued before
@@ -223,7 +228,7 @@ __device__ __forceinline__ uint32_t* dist_live(const Args& a, uint32_t L) {
 // frontier once per level (iteration stamp exchanged atomically).  out[u] is
 // the slot to append to the next frontier, or -1.
 template <int P, int U>
-__device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U],
+__device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const int32_t (&v)[U],
                                             const uint32_t (&w)[U], const Elem (&c)[U],
                                             uint32_t L, int32_t (&out)[U]) {
   int32_t sl[U];
@@ -238,17 +243,27 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
     out[u] = -1;
   }
   if (P == PROB_BFS) {
-    const uint32_t* pb = probe_bits(a, L);
-    uint32_t* cb = claim_bits(a, L);
+    const uint32_t* pb = vis.probe;
+    uint32_t* cb = vis.claim;
     uint32_t word[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? pb[(uint32_t)sl[u] >> 5] : ~0u;
-    // vertices found earlier in this level are still clear in the probed
-    // bitmap: a coherent load of the claim word skips their atomics
+    // split level: vertices found earlier in this level are still clear in
+    // the probed bitmap.  When a batch has many candidates, a coherent load of
+    // the claim word skips their atomics; with few, the extra round trip would
+    // only add latency.
+    uint32_t ncand = 0;
+    if (vis.split) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31))))
-        word[u] = coherent_load(&cb[(uint32_t)sl[u] >> 5]);
+      for (int u = 0; u < U; ++u)
+        ncand += (uint32_t)__popcll(__ballot(sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31)))));
+    }
+    if (ncand > PRECHECK_MIN) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31))))
+          word[u] = coherent_load(&cb[(uint32_t)sl[u] >> 5]);
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t bit = 1u << (sl[u] & 31);
@@ -263,17 +278,25 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
       }
     }
   } else {
-    const uint32_t* dp = dist_probe(a, L);
-    uint32_t* dl = dist_live(a, L);
+    const uint32_t* dp = vis.probe;
+    uint32_t* dl = vis.claim;
     uint32_t nd[U], cur[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       nd[u] = c[u].du + w[u];
       cur[u] = sl[u] >= 0 ? dp[sl[u]] : 0u;
     }
+    uint32_t ncand = 0;
+    if (vis.split) {
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = coherent_load(&dl[sl[u]]);
+      for (int u = 0; u < U; ++u) ncand += (uint32_t)__popcll(__ballot(sl[u] >= 0 && nd[u] < cur[u]));
+    }
+    const bool pre = ncand > PRECHECK_MIN;
+    if (pre) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = coherent_load(&dl[sl[u]]);
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = atomicMin(&dl[sl[u]], nd[u]);
@@ -282,7 +305,7 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
     const uint32_t it = L + 1;
     uint32_t stamp[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) stamp[u] = nd[u] < cur[u] ? coherent_load(&a.visit[sl[u]]) : it;
+    for (int u = 0; u < U; ++u) stamp[u] = (pre && nd[u] < cur[u]) ? coherent_load(&a.visit[sl[u]]) : 0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (nd[u] < cur[u] && stamp[u] != it) stamp[u] = atomicExch(&a.visit[sl[u]], it);
@@ -291,33 +314,6 @@ __device__ __forceinline__ void visit_batch(const Args& a, const int32_t (&v)[U]
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (stamp[u] != it) out[u] = sl[u];
-  }
-}
-
-// Serial version of the child (Sec. III-B): the parent lane walks its own
-// neighbours.  Wave-uniform loop so that appends stay wave-aggregated; U
-// neighbours in flight per lane.
-template <int P>
-__device__ __forceinline__ void serial_children(const Args& a, int32_t start, int32_t cnt,
-                                                const Elem& ctx, uint32_t L, Stage& s,
-                                                LevelSet* ls, int32_t* fout, int lane) {
-  constexpr int U = 8;
-  int32_t e = start;
-  const int32_t end = start + cnt;
-  while (__any(e < end)) {
-    int32_t v[U], out[U];
-    uint32_t w[U];
-    Elem c[U];
-#pragma unroll
-    for (int r = 0; r < U; ++r) {
-      v[r] = (e + r < end) ? a.col[e + r] : -1;
-      w[r] = (P == PROB_SSSP && e + r < end) ? a.w[e + r] : 0u;
-      c[r] = ctx;
-    }
-    visit_batch<P, U>(a, v, w, c, L, out);
-#pragma unroll
-    for (int r = 0; r < U; ++r) stage_push(s, out[r] >= 0, out[r], a, ls, fout, lane);
-    e += U;
   }
 }
 
@@ -432,11 +428,21 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     if (blockIdx.x == 0 && tid == 0) st->done = 1;
     return;
   }
+  // visited copies of this level (every workgroup derives the same choice)
+  const uint32_t vc = st->vsel[L & 1];
+  const bool split = F >= (uint32_t)a.split_min;
+  const bool stale = st->vstale[L & 1] != 0;
+  const Vis vis = vis_of<P>(a, vc, split);
   if (blockIdx.x == 0) {
     LevelSet* z = &st->set[(L + 1) % 3];  // idle until level L + 1
     if (tid <= NQF) z->fcnt[tid] = 0;
     if (tid < NQD) z->qctr[tid] = 0;
-    if (tid == 0) st->levels_run = L + 1;
+    if (tid == 0) {
+      st->levels_run = L + 1;
+      cur->vmode = vc | (split ? 2u : 0u);  // for this level's child kernel
+      st->vsel[(L + 1) & 1] = vc ^ (split ? 1u : 0u);
+      st->vstale[(L + 1) & 1] = (P == PROB_BFS && !split) ? 1u : 0u;
+    }
   }
   if (G == AGG_MULTI) {
     const uint32_t nz = (L + 1) % 3;
@@ -452,11 +458,16 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   if (tid == 0) s_ser[0] = 0;  // thresholded parents listed by this workgroup
   __syncthreads();
 
-  // The copy updated at this level gets the frontier's own vertices (the
-  // previous level's discoveries / improvements): one atomic per frontier
-  // entry, or, for a BFS frontier with more entries than bitmap words, one per
-  // non-zero word of the probed bitmap.
-  const bool word_fold = P == PROB_BFS && F > (uint32_t)a.vwords;
+  // Fold into the copy not probed at this level: one atomic per frontier
+  // entry, or, for BFS after a one-copy level or with more frontier entries
+  // than bitmap words, one per non-zero word of the probed bitmap.
+  const bool word_fold = P == PROB_BFS && split && (stale || F > (uint32_t)a.vwords);
+  const bool entry_fold = P == PROB_SSSP || (split && !word_fold);
+  // a workgroup with at most one virtual block keeps its thresholded parents
+  // in registers (narrow levels are latency-bound)
+  const bool in_regs = nvb <= gridDim.x;
+  int32_t e = 0, end = 0;     // this lane's serial child: edges [e, end)
+  Elem ctx{0, 0, 0, 0, 0u};
 
   // ---- pass 1: every frontier entry once.  Threshold, coarsened grid size,
   // aggregation and launch records; thresholded parents go to this
@@ -475,10 +486,10 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       ++cn.front;
       atomicOr(&s_live[p.q >> 5], 1u << (p.q & 31));
       if (P == PROB_SSSP) {
-        du = dist_probe(a, L)[slot];
-        atomicMin(&dist_live(a, L)[slot], du);
-      } else if (!word_fold) {
-        atomicOr(&claim_bits(a, L)[(uint32_t)slot >> 5], 1u << (slot & 31));
+        du = vis.probe[slot];
+        atomicMin(&vis.fold[slot], du);
+      } else if (entry_fold) {
+        atomicOr(&vis.fold[(uint32_t)slot >> 5], 1u << (slot & 31));
       }
       launch = G != AGG_FLAT && deg > 0 && deg >= p.T;
       ser = deg > 0 && !launch;
@@ -489,9 +500,15 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       if (ser) {
         ++cn.serial;
         cn.eser += deg;
+        if (in_regs) {
+          e = start;
+          end = start + deg;
+          ctx = p.e;
+          ctx.du = du;
+        }
       }
     }
-    {
+    if (!in_regs) {
       // entry k of the list sits in this workgroup's own virtual blocks
       const unsigned long long m = __ballot(ser);
       uint32_t base = 0;
@@ -626,8 +643,6 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     if (tid == 0) s_ser[1] = 0;  // next list entry
     __syncthreads();
     constexpr int U = 8;
-    int32_t e = 0, end = 0;
-    Elem ctx{0, 0, 0, 0, 0u};
     while (true) {
       const bool idle = e >= end;
       const unsigned long long m = __ballot(idle);
@@ -660,18 +675,16 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         w[r] = (P == PROB_SSSP && e + r < end) ? a.w[e + r] : 0u;
         c[r] = ctx;
       }
-      visit_batch<P, U>(a, v, w, c, L, out);
+      visit_batch<P, U>(a, vis, v, w, c, L, out);
 #pragma unroll
       for (int r = 0; r < U; ++r) stage_push(s, out[r] >= 0, out[r], a, cur, fout, lane);
       e = min(e + U, end);
     }
   }
   if (word_fold) {
-    const uint32_t* pb = probe_bits(a, L);
-    uint32_t* cb = claim_bits(a, L);
     for (uint32_t w = blockIdx.x * PB + tid; w < (uint32_t)a.vwords; w += gridDim.x * PB) {
-      const uint32_t x = pb[w];
-      if (x) atomicOr(&cb[w], x);
+      const uint32_t x = vis.probe[w];
+      if (x) atomicOr(&vis.fold[w], x);
     }
   }
   block_flush(s, a, cur, fout, tid, s_bc);
@@ -794,6 +807,8 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   __syncthreads();
   const uint32_t B = s_qpre[NQD];
   if (B == 0) return;
+  const uint32_t vm = cur->vmode;
+  const Vis vis = vis_of<P>(a, vm & 1u, (vm & 2u) != 0);
   const uint32_t nwaves = gridDim.x * NW, gw = blockIdx.x * NW + wave;
   const uint32_t t0 = (uint32_t)((uint64_t)gw * B / nwaves);
   const uint32_t t1 = (uint32_t)((uint64_t)(gw + 1) * B / nwaves);
@@ -851,7 +866,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
             }
           }
         }
-        visit_batch<P, U>(a, v, w, c, L, out);
+        visit_batch<P, U>(a, vis, v, w, c, L, out);
 #pragma unroll
         for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
       }

@@ -46,7 +46,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("threshold", ctypes.c_int32),
                 ("coarsen", ctypes.c_int32), ("agg", ctypes.c_int32),
                 ("agg_blocks", ctypes.c_int32), ("child_block", ctypes.c_int32),
-                ("steps_per_replay", ctypes.c_int32), ("agg_threshold", ctypes.c_int32)]
+                ("steps_per_replay", ctypes.c_int32), ("agg_threshold", ctypes.c_int32),
+                ("split_min", ctypes.c_int32)]
 
 
 class _Csr(ctypes.Structure):
@@ -82,6 +83,7 @@ class Options:
     child_block: int = 256
     steps_per_replay: int = 0
     agg_threshold: int = 0
+    split_min: int = 65536
 
     def c(self) -> _Options:
         return _Options(*(int(getattr(self, f.name)) for f in fields(self)))
@@ -103,7 +105,8 @@ class Options:
             return "flat"
         g = {0: "none", 1: "wave", 2: "block", 3: f"{self.agg_blocks}-block", 4: "grid"}[self.agg]
         at = f"-A{self.agg_threshold}" if self.agg_threshold else ""
-        return f"T{self.threshold}-CF{self.coarsen}-{g}{at}"
+        sm = f"-S{self.split_min}" if self.split_min != 65536 else ""
+        return f"T{self.threshold}-CF{self.coarsen}-{g}{at}{sm}"
 
 
 _lib = None

@@ -54,7 +54,8 @@ def run_batch(kind, da, qs, bopts, stats=False):
 
 MODES = [dict(), dict(agg=dpo.DPO_AGG_WAVE), dict(agg=dpo.DPO_AGG_BLOCK),
          dict(agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=16), dict(agg=dpo.DPO_AGG_NONE),
-         dict(mode=dpo.DPO_MODE_FLAT), dict(child_block=64, steps_per_replay=2)]
+         dict(mode=dpo.DPO_MODE_FLAT), dict(child_block=64, steps_per_replay=2),
+         dict(split_min=0), dict(split_min=256, steps_per_replay=3)]
 
 
 @pytest.mark.parametrize("common", MODES, ids=[str(m) for m in MODES])
@@ -77,7 +78,10 @@ def test_bfs_batch_matches_oracle_per_query(mixed, common):
     assert got_counts == want_counts, common
 
 
-@pytest.mark.parametrize("common", MODES[:4] + MODES[5:6], ids=[str(m) for m in MODES[:4] + MODES[5:6]])
+SSSP_MODES = MODES[:4] + MODES[5:6] + MODES[7:]
+
+
+@pytest.mark.parametrize("common", SSSP_MODES, ids=[str(m) for m in SSSP_MODES])
 def test_sssp_batch_matches_oracle_per_query(mixed, common):
     graphs, qs, da = mixed
     host, slot0, _ = run_batch("sssp", da, qs, bucket_opts(**common))

@@ -123,6 +123,27 @@ def test_bfs_sweep_s14_permuted_several_sources(s14p):
             check_bfs_stats(g, want, opts, st)
 
 
+@pytest.mark.parametrize("split_min", [0, 512, 1 << 30], ids=["always-split", "switching", "never-split"])
+def test_visited_copies_every_mode(s14p, split_min):
+    """Levels that probe one visited copy and update the other, levels that use
+    one copy, and traversals that switch between the two from level to level
+    (split_min=512 on a scale-14 graph) give the oracle's results, with the
+    workspace reused across sources."""
+    g, dg = s14p
+    srcs = [int(s) for s in gg.sample_sources(g, 3, 5)] + [gg.max_degree_vertex(g)]
+    for base in (dpo.Options(threshold=32, coarsen=1), dpo.Options.naive(), dpo.Options.flat()):
+        opts = dpo.Options(**{**base.__dict__, "split_min": split_min})
+        ws = dpo.alloc_workspace(dg, opts)
+        for s in srcs:
+            print("copies", opts.label(), s, flush=True)
+            want = oracle.bfs(g, s)[0]
+            got, st = run_bfs(dg, s, opts, ws=ws)
+            assert np.array_equal(got, want), (opts.label(), s)
+            check_bfs_stats(g, want, opts, st)
+            got_d, _ = run_sssp(dg, s, opts, ws=ws)
+            assert np.array_equal(got_d, oracle.dijkstra(g, s)), (opts.label(), s)
+
+
 def test_sssp_sweep_s14(s14p):
     g, dg = s14p
     src = gg.max_degree_vertex(g)
