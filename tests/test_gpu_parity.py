@@ -144,6 +144,21 @@ def test_visited_copies_every_mode(s14p, split_min):
             assert np.array_equal(got_d, oracle.dijkstra(g, s)), (opts.label(), s)
 
 
+def test_sssp_distances_beyond_the_bound_code():
+    """Distances from 0 up to ~10^8: small ones have exact bound codes, large
+    ones saturate to "unknown"; both must give the oracle's distances."""
+    base = gg.add_weights(gg.grid_graph(60, 55), 77)
+    for scale in (1, 4099):
+        g = gg.Graph(row_ptr=base.row_ptr, col_idx=base.col_idx,
+                     weights=(base.weights.astype(np.uint64) * scale).astype(np.uint32))
+        dg = dpo.DeviceGraph.from_host(g)
+        for opts in (dpo.Options(threshold=2, coarsen=1), dpo.Options(split_min=0), dpo.Options.naive()):
+            want = oracle.dijkstra(g, 0)
+            print("big distances", scale, opts.label(), int(want.max()), flush=True)
+            got, _ = run_sssp(dg, 0, opts)
+            assert np.array_equal(got, want), (scale, opts.label())
+
+
 def test_sssp_sweep_s14(s14p):
     g, dg = s14p
     src = gg.max_degree_vertex(g)
