@@ -42,7 +42,8 @@ def parse():
     p.add_argument("--threshold", type=int, default=None)
     p.add_argument("--coarsen", type=int, default=None)
     p.add_argument("--agg", default=None, help="none|wave|block|<k>-block")
-    p.add_argument("--sweep", action="store_true", help="config-2 sweep table instead")
+    p.add_argument("--sweep", action="store_true",
+                   help="threshold x coarsening x granularity sweep of the workload instead")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-baselines", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -73,7 +74,8 @@ def agg_of(s):
     return (dpo.DPO_AGG_MULTIBLOCK, int(s.split("-")[0]))
 
 
-# Best point of the config-2 sweep on MI355X; overridable.
+# Best point of the s22 BFS sweep (threshold x coarsening x granularity) on
+# MI355X; overridable from the command line.
 TUNED = {"bfs22": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4)}
@@ -312,7 +314,7 @@ def main():
         return summarize_profiles(args, args.summarize_profiles)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "independent traversals shard by graph across GPUs, see DESIGN.md", file=sys.stderr)
+              "(independent traversals shard by graph across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2201_02789_amd import dpo
@@ -640,13 +642,14 @@ def bench_road(args, dpo, torch):
 
 
 def sweep(dpo, torch, wl, dg):
-    """Config-2 sweep: T x CF x granularity, plus flat and naive (JSON lines)."""
+    """Sweep of T x CF x granularity (and the aggregation threshold), plus flat
+    and naive, on the workload's graph and sources (JSON lines)."""
     import itertools
     rs = reached_stats(dpo, torch, wl, dg, dpo.Options())
     edges = float(sum(r[0] for r in rs) / 2)
     steps = max(r[2]["levels"] for r in rs) + 1
     grid = [dpo.Options.flat(), dpo.Options.naive()]
-    for T, CF, (agg, k) in itertools.product([0, 8, 32, 128, 512], [1, 2, 4, 8],
+    for T, CF, (agg, k) in itertools.product([0, 8, 16, 32, 64, 128, 512], [1, 2, 4, 8],
                                              [(1, 4), (2, 4), (3, 4), (3, 16), (4, 4)]):
         grid.append(dpo.Options(threshold=T, coarsen=CF, agg=agg, agg_blocks=k))
     for T, agg, at in itertools.product([8, 32], [1, 2], [8, 32]):  # aggregation threshold

@@ -111,7 +111,7 @@ def test_repeated_queries_identical(mixed):
 
 
 @pytest.mark.slow
-def test_batch_config_512_queries_bfs():
+def test_batch_512_queries_over_64_graphs_bfs():
     """The batched workload: 512 BFS over 64 R-MAT graphs, scales 10..18."""
     graphs, queries = gg.batch_workload()
     arena, vbase = gg.pack_arena(graphs)

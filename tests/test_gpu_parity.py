@@ -67,16 +67,16 @@ def check_bfs_stats(g, lv, opts, st):
 
 @pytest.fixture(scope="module")
 def s12():
-    """Config 1: R-MAT scale 12, ef 16, unpermuted (vertex 0 is the hub)."""
+    """R-MAT scale 12, ef 16, unpermuted (vertex 0 is the hub)."""
     g = gg.rmat(12, 16, 1)
     return g, dpo.DeviceGraph.from_host(g)
 
 
-def test_config1_naive_bfs_s12(s12):
+def test_naive_bfs_s12_from_hub(s12):
     g, dg = s12
     want, _ = oracle.bfs(g, 0)
     got, st = run_bfs(dg, 0, dpo.Options.naive())
-    print("config1 naive", st, flush=True)
+    print("s12 naive", st, flush=True)
     assert np.array_equal(got, want)
     cert.check_bfs(g, 0, got)
     check_bfs_stats(g, want, dpo.Options.naive(), st)
@@ -222,7 +222,7 @@ def test_errors_reported():
 
 @pytest.fixture(scope="module")
 def s22():
-    """Config 2: R-MAT scale 22, ef 16, permuted, 16 sources."""
+    """R-MAT scale 22, ef 16, permuted, 16 sources (the BFS headline workload)."""
     g = gg.rmat(22, 16, 22, perm_seed=24)
     return g, dpo.DeviceGraph.from_host(g), gg.sample_sources(g, 16, 1)
 
