@@ -76,9 +76,9 @@ def agg_of(s):
 
 # Best point of the s22 BFS sweep (threshold x coarsening x granularity) on
 # MI355X; overridable from the command line.
-TUNED = {"bfs22": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4),
+TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
-         "sssp21": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4)}
+         "sssp21": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4)}
 
 
 class Workload:
