@@ -35,7 +35,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="bfs22",
-                   choices=["bfs22", "sssp21", "bfs12", "batch", "serve", "road"])
+                   choices=["bfs22", "er22", "sssp21", "bfs12", "batch", "serve", "road"])
     p.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
     p.add_argument("--serve-seconds", type=float, default=0.5)
     p.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
@@ -77,6 +77,7 @@ def agg_of(s):
 # Best point of the s22 BFS sweep (threshold x coarsening x granularity) on
 # MI355X; overridable from the command line.
 TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
+         "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4)}
 
@@ -91,6 +92,16 @@ class Workload:
             self.sources = gg.sample_sources(self.g, 16, 1)
             self.kind = "bfs"
             self.desc = "BFS, R-MAT scale 22, edgefactor 16, a/b/c/d .57/.19/.19/.05, permuted, 16 sources"
+        elif name == "er22":
+            # Erdos-Renyi control: same n and the same number of undirected edges as
+            # the s22 R-MAT graph, Poisson degrees instead of a power law
+            r = gg.rmat(22, 16, 22, perm_seed=24)
+            self.g = gg.erdos_renyi(r.n, r.m // 2, 23)
+            del r
+            self.sources = gg.sample_sources(self.g, 16, 1)
+            self.kind = "bfs"
+            self.desc = ("BFS, Erdos-Renyi G(n, M) with the s22 R-MAT graph's n and undirected "
+                         "edge count, 16 sources")
         elif name == "bfs12":
             self.g = gg.rmat(12, 16, 1)
             self.sources = np.array([0], dtype=np.int32)
@@ -188,6 +199,20 @@ def algorithmic_bytes(kind, m_r, n_r):
     return (8 * m_r + 20 * n_r) if kind == "bfs" else (12 * m_r + 24 * n_r)
 
 
+def host_cpu():
+    """CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} usable cores"
+
+
 def cpu_baseline(wl, min_seconds=10.0, max_seconds=30.0):
     """The oracle on this host, single thread, over the workload's sources in
     order (repeated if need be) until at least min_seconds of work."""
@@ -208,7 +233,7 @@ def cpu_baseline(wl, min_seconds=10.0, max_seconds=30.0):
         if dt * (runs + 1) / runs > max_seconds:
             break
     return {"value": round(edges / 2 / dt / 1e9, 4), "unit": "GTEPS", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": f"{runs} traversals over the workload's {len(wl.sources)} source(s) in order, "
                       f"one full {'queue BFS' if wl.kind == 'bfs' else 'binary-heap Dijkstra'} each, "
                       f"single thread, {dt:.1f} s"}
@@ -414,13 +439,19 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
-        "data": "synthetic (seeded R-MAT, stands in for the paper's Kronecker graph)",
+        "data": ("synthetic (seeded Erdos-Renyi control)" if args.workload == "er22" else
+                 "synthetic (seeded R-MAT, stands in for the paper's Kronecker graph)"),
         "config": {"workload": wl.desc, "n": wl.g.n, "m": wl.g.m,
                    "sources": int(len(wl.sources)), "options": opts.label(),
                    "steps_per_replay": opts.steps_per_replay,
                    "mean_reached_edges": float(m_r.mean()),
                    "gteps_convention": "undirected edges in the reached component / time, "
-                                       "summed over sources"},
+                                       "summed over sources",
+                   "directed_edges_per_s": round(2 * gteps * 1e9),
+                   # edges the traversal actually relaxes per reached directed edge
+                   # (1 for BFS; above 1 for the frontier Bellman-Ford of SSSP)
+                   "work_efficiency": round(float(np.mean(
+                       [(r[2]["edges_serial"] + r[2]["edges_child"]) / max(r[0], 1) for r in rs])), 3)},
         "roofline": roofline,
         "baselines": baselines,
         "speedup_vs_flat": round(gteps / baselines["flat"]["gteps"], 2) if baselines else None,

@@ -159,6 +159,24 @@ def test_sssp_distances_beyond_the_bound_code():
             assert np.array_equal(got, want), (scale, opts.label())
 
 
+def test_relabelled_graph_gives_permuted_outputs(s14p):
+    """Metamorphic: renaming vertex v to perm[v] permutes the GPU outputs the
+    same way (the frontier order, records and aggregation all change)."""
+    g, dg = s14p
+    perm = gg.permutation(g.n, 77)
+    h = gg.relabel(g, perm)
+    dh = dpo.DeviceGraph.from_host(h)
+    for opts in (dpo.Options(threshold=64, coarsen=1), dpo.Options.naive(), dpo.Options(split_min=0)):
+        for s in [int(x) for x in gg.sample_sources(g, 2, 9)]:
+            print("relabel", opts.label(), s, flush=True)
+            a, _ = run_bfs(dg, s, opts)
+            b, _ = run_bfs(dh, int(perm[s]), opts)
+            assert np.array_equal(b[perm], a), (opts.label(), s)
+            da, _ = run_sssp(dg, s, opts)
+            db, _ = run_sssp(dh, int(perm[s]), opts)
+            assert np.array_equal(db[perm], da), (opts.label(), s)
+
+
 def test_sssp_sweep_s14(s14p):
     g, dg = s14p
     src = gg.max_degree_vertex(g)
