@@ -333,6 +333,106 @@ def summarize_profiles(args, d):
                       "traffic": traffic}))
 
 
+def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baselines, overrides=True):
+    """Measures one traversal workload; returns its JSON line (None for --sweep).
+    `overrides`: apply the command line's threshold / coarsening / granularity."""
+    wl = Workload(name)
+    dg = dpo.DeviceGraph.from_host(wl.g)
+    tuned = dict(TUNED[name])
+    if overrides and args.threshold is not None:
+        tuned["threshold"] = args.threshold
+    if overrides and args.coarsen is not None:
+        tuned["coarsen"] = args.coarsen
+    a = agg_of(args.agg) if overrides else None
+    if a:
+        tuned["agg"], tuned["agg_blocks"] = a
+    opts = dpo.Options(**tuned)
+
+    if args.sweep:
+        sweep(dpo, torch, wl, dg)
+        return None
+
+    # untimed run with counters: edges reached and level count per source
+    rs = reached_stats(dpo, torch, wl, dg, opts)
+    levels = max(r[2]["levels"] for r in rs)
+    opts.steps_per_replay = levels + 1  # one replay covers a traversal
+    m_r = np.array([r[0] for r in rs], dtype=np.float64)
+    n_r = np.array([r[1] for r in rs], dtype=np.float64)
+    log(f"[bench] options {opts.label()} steps/replay {opts.steps_per_replay}; "
+        f"m_r mean {m_r.mean():.0f}, n_r mean {n_r.mean():.0f}")
+
+    per_call, wall = measure(dpo, torch, wl, dg, opts, steps, warmup)
+    t_step_ms = per_call.sum(axis=1)  # ms per step (all sources)
+    total_ms = float(per_call.sum())
+    edges_step = float((m_r / 2).sum())
+    gteps = steps * edges_step / (total_ms * 1e-3) / 1e9
+    log(f"[bench] T+C+A: {gteps:.2f} GTEPS, {t_step_ms.mean():.3f} ms/step, wall {wall:.3f}s")
+
+    # roofline of the level-step kernel: algorithmic bytes per launch / mean
+    # launch duration, both per traversal divided by its launch count
+    launches = np.array([r[2]["levels"] + 1 for r in rs], dtype=np.float64)
+    bytes_call = algorithmic_bytes(wl.kind, m_r, n_r)
+    mean_call_ms = per_call.mean(axis=0)
+    achieved = float((bytes_call.sum() / launches.sum()) /
+                     ((mean_call_ms.sum() * 1e-3) / launches.sum()) / 1e9)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(name, opts.label()),
+                "kernel": f"level step: parent_kernel + child_kernel <{wl.kind.upper()}, {opts.label()}>",
+                "launches_per_traversal": float(launches.mean()),
+                "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
+                "algorithmic_bytes_per_launch": round(float(bytes_call.sum() / launches.sum()))}
+
+    baselines = {}
+    if with_baselines:
+        for name, o in (("flat", dpo.Options.flat()), ("naive", dpo.Options.naive())):
+            o.steps_per_replay = opts.steps_per_replay
+            pc, _ = measure(dpo, torch, wl, dg, o, 1, 1)
+            g_b = edges_step / (pc.sum() * 1e-3) / 1e9
+            baselines[name] = {"gteps": round(g_b, 3), "ms_per_step": round(float(pc.sum()), 3),
+                               "options": o.label()}
+            log(f"[bench] {name}: {g_b:.3f} GTEPS")
+
+    cpu = None
+    if with_cpu:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+        log(f"[bench] oracle: {cpu['value']} GTEPS ({cpu['sample']})")
+
+    line = {
+        "metric": "GTEPS (BFS/SSSP, R-MAT s22) vs flat & naive-nested",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(float(t_step_ms.mean()), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": ("synthetic (seeded Erdos-Renyi control)" if name == "er22" else
+                 "synthetic (seeded R-MAT, stands in for the paper's Kronecker graph)"),
+        "config": {"workload": wl.desc, "n": wl.g.n, "m": wl.g.m,
+                   "sources": int(len(wl.sources)), "options": opts.label(),
+                   "steps_per_replay": opts.steps_per_replay,
+                   "mean_reached_edges": float(m_r.mean()),
+                   "gteps_convention": "undirected edges in the reached component / time, "
+                                       "summed over sources",
+                   "directed_edges_per_s": round(2 * gteps * 1e9),
+                   # edges the traversal actually relaxes per reached directed edge
+                   # (1 for BFS; above 1 for the frontier Bellman-Ford of SSSP)
+                   "work_efficiency": round(float(np.mean(
+                       [(r[2]["edges_serial"] + r[2]["edges_child"]) / max(r[0], 1) for r in rs])), 3)},
+        "roofline": roofline,
+        "baselines": baselines,
+        "speedup_vs_flat": round(gteps / baselines["flat"]["gteps"], 2) if baselines else None,
+        "speedup_vs_naive": round(gteps / baselines["naive"]["gteps"], 2) if baselines else None,
+        "cpu_baseline": cpu,
+    }
+    line["_graph"] = (wl, dg)
+    return line
+
+
 def main():
     args = parse()
     if args.summarize_profiles:
@@ -366,100 +466,19 @@ def main():
     if args.workload == "road":
         print(json.dumps(bench_road(args, dpo, torch)), flush=True)
         return
-    wl = Workload(args.workload)
-    dg = dpo.DeviceGraph.from_host(wl.g)
-    tuned = dict(TUNED[args.workload])
-    if args.threshold is not None:
-        tuned["threshold"] = args.threshold
-    if args.coarsen is not None:
-        tuned["coarsen"] = args.coarsen
-    a = agg_of(args.agg)
-    if a:
-        tuned["agg"], tuned["agg_blocks"] = a
-    opts = dpo.Options(**tuned)
-
-    if args.sweep:
-        return sweep(dpo, torch, wl, dg)
-
-    # untimed run with counters: edges reached and level count per source
-    rs = reached_stats(dpo, torch, wl, dg, opts)
-    levels = max(r[2]["levels"] for r in rs)
-    opts.steps_per_replay = levels + 1  # one replay covers a traversal
-    m_r = np.array([r[0] for r in rs], dtype=np.float64)
-    n_r = np.array([r[1] for r in rs], dtype=np.float64)
-    log(f"[bench] options {opts.label()} steps/replay {opts.steps_per_replay}; "
-        f"m_r mean {m_r.mean():.0f}, n_r mean {n_r.mean():.0f}")
-
-    per_call, wall = measure(dpo, torch, wl, dg, opts, args.steps, args.warmup)
-    t_step_ms = per_call.sum(axis=1)  # ms per step (all sources)
-    total_ms = float(per_call.sum())
-    edges_step = float((m_r / 2).sum())
-    gteps = args.steps * edges_step / (total_ms * 1e-3) / 1e9
-    log(f"[bench] T+C+A: {gteps:.2f} GTEPS, {t_step_ms.mean():.3f} ms/step, wall {wall:.3f}s")
-
-    # roofline of the level-step kernel: algorithmic bytes per launch / mean
-    # launch duration, both per traversal divided by its launch count
-    launches = np.array([r[2]["levels"] + 1 for r in rs], dtype=np.float64)
-    bytes_call = algorithmic_bytes(wl.kind, m_r, n_r)
-    mean_call_ms = per_call.mean(axis=0)
-    achieved = float((bytes_call.sum() / launches.sum()) /
-                     ((mean_call_ms.sum() * 1e-3) / launches.sum()) / 1e9)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, opts.label()),
-                "kernel": f"level step: parent_kernel + child_kernel <{wl.kind.upper()}, {opts.label()}>",
-                "launches_per_traversal": float(launches.mean()),
-                "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
-                "algorithmic_bytes_per_launch": round(float(bytes_call.sum() / launches.sum()))}
-
-    baselines = {}
-    if not args.no_baselines:
-        for name, o in (("flat", dpo.Options.flat()), ("naive", dpo.Options.naive())):
-            o.steps_per_replay = opts.steps_per_replay
-            pc, _ = measure(dpo, torch, wl, dg, o, 1, 1)
-            g_b = edges_step / (pc.sum() * 1e-3) / 1e9
-            baselines[name] = {"gteps": round(g_b, 3), "ms_per_step": round(float(pc.sum()), 3),
-                               "options": o.label()}
-            log(f"[bench] {name}: {g_b:.3f} GTEPS")
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_seconds)
-        log(f"[bench] oracle: {cpu['value']} GTEPS ({cpu['sample']})")
-
-    line = {
-        "metric": "GTEPS (BFS/SSSP, R-MAT s22) vs flat & naive-nested",
-        "value": round(gteps, 3),
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(float(t_step_ms.mean()), 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": ("synthetic (seeded Erdos-Renyi control)" if args.workload == "er22" else
-                 "synthetic (seeded R-MAT, stands in for the paper's Kronecker graph)"),
-        "config": {"workload": wl.desc, "n": wl.g.n, "m": wl.g.m,
-                   "sources": int(len(wl.sources)), "options": opts.label(),
-                   "steps_per_replay": opts.steps_per_replay,
-                   "mean_reached_edges": float(m_r.mean()),
-                   "gteps_convention": "undirected edges in the reached component / time, "
-                                       "summed over sources",
-                   "directed_edges_per_s": round(2 * gteps * 1e9),
-                   # edges the traversal actually relaxes per reached directed edge
-                   # (1 for BFS; above 1 for the frontier Bellman-Ford of SSSP)
-                   "work_efficiency": round(float(np.mean(
-                       [(r[2]["edges_serial"] + r[2]["edges_child"]) / max(r[0], 1) for r in rs])), 3)},
-        "roofline": roofline,
-        "baselines": baselines,
-        "speedup_vs_flat": round(gteps / baselines["flat"]["gteps"], 2) if baselines else None,
-        "speedup_vs_naive": round(gteps / baselines["naive"]["gteps"], 2) if baselines else None,
-        "cpu_baseline": cpu,
-    }
+    line = workload_line(args, dpo, torch, args.workload, args.steps, args.warmup,
+                         not args.no_cpu, not args.no_baselines)
+    if line is None:
+        return
+    del line["_graph"]
     if not args.no_extras and args.workload == "bfs22":
-        del dg, wl
+        torch.cuda.empty_cache()
+        # the SSSP half of the metric: s21, tuned options, flat and naive beside it
+        sp = workload_line(args, dpo, torch, "sssp21", 3, 1, False, True, overrides=False)
+        del sp["_graph"]
+        line["sssp"] = {k: sp[k] for k in ("value", "unit", "ms_per_step", "dtype", "config",
+                                             "roofline", "baselines", "speedup_vs_flat",
+                                             "speedup_vs_naive")}
         torch.cuda.empty_cache()
         line["batched"] = bench_batch(args, dpo, torch)
         line["serving"] = bench_serve(args, dpo, torch)
