@@ -177,6 +177,25 @@ def test_relabelled_graph_gives_permuted_outputs(s14p):
             assert np.array_equal(db[perm], da), (opts.label(), s)
 
 
+def test_csr_arrays_not_16_byte_aligned(s14p):
+    """col_idx and weights that start 4 bytes into larger buffers (device
+    pointers the kernels may not assume to be 16-byte aligned) give the same
+    results."""
+    g, dg = s14p
+    col = torch.zeros(g.m + 1, dtype=torch.int32, device="cuda")
+    col[1:] = dg.col_idx
+    w = torch.zeros(g.m + 1, dtype=torch.int32, device="cuda")
+    w[1:] = dg.weights
+    du = dpo.DeviceGraph(dg.row_ptr, col[1:], w[1:])
+    assert du.col_idx.data_ptr() % 16 == 4
+    s = gg.max_degree_vertex(g)
+    for opts in (dpo.Options(threshold=64, coarsen=1), dpo.Options.flat()):
+        got, _ = run_bfs(du, s, opts)
+        assert np.array_equal(got, oracle.bfs(g, s)[0]), opts.label()
+        got_d, _ = run_sssp(du, s, opts)
+        assert np.array_equal(got_d, oracle.dijkstra(g, s)), opts.label()
+
+
 def test_sssp_sweep_s14(s14p):
     g, dg = s14p
     src = gg.max_degree_vertex(g)
