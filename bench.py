@@ -514,6 +514,9 @@ def bench_batch(args, dpo, torch, full_line=False):
     edges = 0
     for i, (g, s, b) in enumerate(qs):
         edges += int(deg[g][host[slot0[i]:slot0[i] + graphs[g].n] >= 0].sum())
+    # one replay covers the batch (the counted run gave its level count)
+    for o in tuned:
+        o.steps_per_replay = st["levels"] + 1
     steps, warm = max(1, args.steps), max(1, args.warmup)
     for _ in range(warm):
         dpo.dpo_bfs_batch(da, qs, tuned, out, ws)
@@ -546,7 +549,8 @@ def bench_batch(args, dpo, torch, full_line=False):
     per = (time.perf_counter() - t1) / len(sub)
     res["one_by_one_traversals_per_s"] = round(1.0 / per, 1)
     del dgs, bufs
-    # untuned: every bucket at the base point
+    # untuned: every bucket at the base point (same replay length)
+    base.steps_per_replay = st["levels"] + 1
     qs0 = [(g, s, 0) for g, s, _ in qs]
     dpo.dpo_bfs_batch(da, qs0, [base], out, ws)
     torch.cuda.synchronize()

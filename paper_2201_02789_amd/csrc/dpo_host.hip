@@ -77,7 +77,7 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   size_t off = 0;
   L.state = off; off = align_up(off + sizeof(State));
   L.queries = off; off = align_up(off + (size_t)nq * sizeof(Query));
-  L.qlist = off; off = align_up(off + (size_t)nq * 4);
+  L.qlist = off; off = align_up(off + (size_t)(2 * nq + 1) * 4);  // list + workgroup prefix
   L.qmap = off; off = align_up(off + (size_t)cdiv(slots, 32) * 4);
   L.grp_packed = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 8);
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
@@ -137,7 +137,7 @@ struct Runtime {
   uint32_t* host_flags = nullptr;  // pinned: base, done, error, levels_run
   unsigned long long* host_stats = nullptr;  // pinned: MAX_GRID * NSTAT
   Query* host_q = nullptr;                   // pinned: MAX_QUERIES query records
-  int32_t* host_list = nullptr;              // pinned: MAX_QUERIES query indices
+  int32_t* host_list = nullptr;              // pinned: MAX_QUERIES query indices + prefix
   int cu_count = 0;
   std::vector<GridEntry> grids;
 };
@@ -156,7 +156,7 @@ dpo_status ensure_runtime(Runtime& r) {
   if (hipDeviceGetAttribute(&r.cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return DPO_ERR_HIP;
   void* p = nullptr;
-  const size_t qbytes = (size_t)MAX_QUERIES * (sizeof(Query) + 4);
+  const size_t qbytes = (size_t)MAX_QUERIES * (sizeof(Query) + 8) + 4;
   if (hipHostMalloc(&p, 256 + (size_t)MAX_GRID * NSTAT * 8 + qbytes, hipHostMallocDefault) !=
       hipSuccess)
     return DPO_ERR_HIP;
@@ -322,21 +322,26 @@ int init_grid(Runtime& r, int64_t work) {
   return (int)std::max<int64_t>(gsz, 1);
 }
 
-// Start the queries hlist[0 .. count) whose records are already in hq (host,
-// pinned): upload those records and the index list, then the admit kernels.
-dpo_status admit(Runtime& r, SetRun& sr, const Query* hq, const int32_t* hlist, int32_t count,
-                 int32_t reset, int64_t work) {
-  if (count <= 0) return DPO_OK;
-  for (int32_t k = 0; k < count; ++k)
-    if (hipMemcpyAsync(sr.a.q + hlist[k], hq + hlist[k], sizeof(Query), hipMemcpyHostToDevice,
-                       sr.stream) != hipSuccess)
-      return DPO_ERR_HIP;
-  if (hipMemcpyAsync(sr.qlist, hlist, (size_t)count * 4, hipMemcpyHostToDevice, sr.stream) !=
-      hipSuccess)
+// Admit workgroups: hlist[count + k] = first workgroup of query hlist[k]
+// (one per ADMIT_CHUNK of its slots, at least one); returns the total.
+int32_t admit_prefix(const Query* hq, int32_t* hlist, int32_t count) {
+  int32_t* pre = hlist + count;
+  int64_t t = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    pre[k] = (int32_t)t;
+    t += std::max<int64_t>(1, cdiv(hq[hlist[k]].n, ADMIT_CHUNK));
+  }
+  pre[count] = (int32_t)t;
+  return (int32_t)t;
+}
+
+dpo_status launch_admit(SetRun& sr, int32_t* hlist, int32_t count, int32_t reset, int32_t groups) {
+  if (hipMemcpyAsync(sr.qlist, hlist, (size_t)(2 * count + 1) * 4, hipMemcpyHostToDevice,
+                     sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
   int32_t* dl = sr.qlist;
   void* p1[] = {&sr.a, &dl, &count, &reset};
-  if (hipLaunchKernel(admit_kernel_ptr(sr.problem), dim3(init_grid(r, work)), dim3(PB), p1, 0,
+  if (hipLaunchKernel(admit_kernel_ptr(sr.problem), dim3((unsigned)groups), dim3(PB), p1, 0,
                       sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
   void* p2[] = {&sr.a, &dl, &count};
@@ -346,26 +351,27 @@ dpo_status admit(Runtime& r, SetRun& sr, const Query* hq, const int32_t* hlist, 
   return DPO_OK;
 }
 
+// Start the queries hlist[0 .. count) whose records are already in hq (host,
+// pinned; hlist has room for 2 * count + 1 entries): upload those records,
+// the index list and the workgroup prefix, then the admit kernels.
+dpo_status admit(Runtime& r, SetRun& sr, const Query* hq, int32_t* hlist, int32_t count,
+                 int32_t reset) {
+  (void)r;
+  if (count <= 0) return DPO_OK;
+  for (int32_t k = 0; k < count; ++k)
+    if (hipMemcpyAsync(sr.a.q + hlist[k], hq + hlist[k], sizeof(Query), hipMemcpyHostToDevice,
+                       sr.stream) != hipSuccess)
+      return DPO_ERR_HIP;
+  return launch_admit(sr, hlist, count, reset, admit_prefix(hq, hlist, count));
+}
+
 // Batch start: the whole table in one upload, then the admit kernels.
-dpo_status admit_all(Runtime& r, SetRun& sr, const Query* hq, const int32_t* hlist, int32_t nq,
-                     int64_t work) {
+dpo_status admit_all(Runtime& r, SetRun& sr, const Query* hq, int32_t* hlist, int32_t nq) {
+  (void)r;
   if (hipMemcpyAsync(sr.a.q, hq, (size_t)nq * sizeof(Query), hipMemcpyHostToDevice, sr.stream) !=
       hipSuccess)
     return DPO_ERR_HIP;
-  if (hipMemcpyAsync(sr.qlist, hlist, (size_t)nq * 4, hipMemcpyHostToDevice, sr.stream) !=
-      hipSuccess)
-    return DPO_ERR_HIP;
-  int32_t* dl = sr.qlist;
-  int32_t reset = 0;
-  void* p1[] = {&sr.a, &dl, &nq, &reset};
-  if (hipLaunchKernel(admit_kernel_ptr(sr.problem), dim3(init_grid(r, work)), dim3(PB), p1, 0,
-                      sr.stream) != hipSuccess)
-    return DPO_ERR_HIP;
-  void* p2[] = {&sr.a, &dl, &nq};
-  if (hipLaunchKernel(admit_sources_kernel_ptr(), dim3((unsigned)cdiv(nq, PB)), dim3(PB), p2, 0,
-                      sr.stream) != hipSuccess)
-    return DPO_ERR_HIP;
-  return DPO_OK;
+  return launch_admit(sr, hlist, nq, 0, admit_prefix(hq, hlist, nq));
 }
 
 dpo_status start_set(Runtime& r, SetRun& sr) {
@@ -444,7 +450,7 @@ dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_opt
   int32_t* hl = r.host_list;
   hl[0] = 0;
   if ((s = start_set(r, sr)) != DPO_OK) return s;
-  if ((s = admit(r, sr, hq, hl, 1, 0, g->n)) != DPO_OK) return s;
+  if ((s = admit(r, sr, hq, hl, 1, 0)) != DPO_OK) return s;
   if ((s = run_to_completion(r, sr, g->n)) != DPO_OK) return s;
   return read_stats(r, sr, st);
 }
@@ -484,13 +490,11 @@ dpo_status traverse_batch(int problem, const dpo_arena* ar, const dpo_query* qs,
   if (problem == PROB_SSSP && ar->csr.n > 16843009) return DPO_ERR_ARG;
   const int64_t slots = batch_slots(ar, qs, nq, nullptr);
   if (slots < 0) return DPO_ERR_ARG;
-  int64_t max_n = 0;
   for (int32_t i = 0; i < nq; ++i) {
     const int32_t g = qs[i].graph;
     const int32_t n = ar->graph_vbase[g + 1] - ar->graph_vbase[g];
     if (qs[i].source < 0 || qs[i].source >= n) return DPO_ERR_SOURCE;
     if (qs[i].bucket < 0 || qs[i].bucket >= nb) return DPO_ERR_ARG;
-    max_n = std::max<int64_t>(max_n, n);
   }
   if (ws_bytes < layout_for(slots, nq, bopts[0]).total) return DPO_ERR_WORKSPACE;
   Runtime& r = rt();
@@ -514,7 +518,7 @@ dpo_status traverse_batch(int problem, const dpo_arena* ar, const dpo_query* qs,
   int32_t* hl = r.host_list;
   for (int32_t i = 0; i < nq; ++i) hl[i] = i;
   if ((s = start_set(r, sr)) != DPO_OK) return s;
-  if ((s = admit_all(r, sr, hq, hl, nq, max_n)) != DPO_OK) return s;
+  if ((s = admit_all(r, sr, hq, hl, nq)) != DPO_OK) return s;
   if ((s = run_to_completion(r, sr, slots)) != DPO_OK) return s;
   return read_stats(r, sr, st);
 }
@@ -631,7 +635,6 @@ dpo_status engine_step(dpo_engine* e) {
   // admit in arrival order while a table entry and the footprint fit
   int32_t count = 0;
   const bool reset = e->running == 0;
-  int64_t work = 0;
   while (!e->pending.empty() && !e->free_q.empty()) {
     const Pending& p = e->pending.front();
     const int32_t n = e->vbase[p.graph + 1] - e->vbase[p.graph];
@@ -650,7 +653,6 @@ dpo_status engine_step(dpo_engine* e) {
     ru.slot0 = slot0;
     ru.footprint = round32(n);
     e->hlist[count++] = q;
-    work = std::max<int64_t>(work, n);
     ++e->running;
     e->pending.pop_front();
   }
@@ -659,7 +661,7 @@ dpo_status engine_step(dpo_engine* e) {
       // nothing was running: restart the level sets (and their counters)
       if ((s = start_set(r, sr)) != DPO_OK) return s;
     }
-    if ((s = admit(r, sr, e->hq, e->hlist, count, 0, work)) != DPO_OK) return s;
+    if ((s = admit(r, sr, e->hq, e->hlist, count, 0)) != DPO_OK) return s;
   }
   if (e->running > 0) {
     if (hipGraphLaunch(e->exec, sr.stream) != hipSuccess) return DPO_ERR_HIP;
@@ -725,7 +727,7 @@ dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_opt
                   ws_bytes, stream, false, &e->sr);
   void* p = nullptr;
   if (s == DPO_OK &&
-      hipHostMalloc(&p, 64 + (size_t)max_queries * (sizeof(Query) + 4), hipHostMallocDefault) !=
+      hipHostMalloc(&p, 64 + (size_t)max_queries * (sizeof(Query) + 8) + 4, hipHostMallocDefault) !=
           hipSuccess)
     s = DPO_ERR_HIP;
   if (s == DPO_OK) {

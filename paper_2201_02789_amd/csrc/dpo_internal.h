@@ -13,6 +13,7 @@ constexpr int NQF = 64;          // frontier queues (queue = workgroup % 64), pl
 constexpr int MAX_GRID = 4096;   // persistent grid cap (rows of the per-workgroup counters)
 constexpr int NSTAT = 8;
 constexpr int MAX_QUERIES = 4096;  // per-query tables are staged in LDS
+constexpr int ADMIT_CHUNK = 4096;  // output slots initialised per admit workgroup
 constexpr int PRECHECK_MIN = 32;   // claim candidates per 512-lane batch above which
                                    // a coherent load precedes the atomics
 

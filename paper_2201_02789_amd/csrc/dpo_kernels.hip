@@ -909,40 +909,51 @@ __global__ __launch_bounds__(PB) void init_kernel(Args a) {
 }
 
 // Starts the queries list[0 .. count) at level index L = st->base: their
-// outputs set to "unreached" except the source, their visit words cleared and
-// their 32-slot chunks mapped to them.  `reset` (host-known: every earlier
-// query has finished) also clears the level sets, whose fills are then stale.
+// outputs set to "unreached" except the source, their visit state cleared and
+// their 32-slot chunks mapped to them.  Query list[k] is served by the
+// workgroups [pre[k], pre[k + 1]) (pre = list + count, a host-built prefix of
+// per-query workgroup counts proportional to n), so a batch of many small
+// queries does not leave most of the grid idle.  `reset` (host-known: every
+// earlier query has finished) also clears the level sets, whose fills are then
+// stale.
 template <int P>
 __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, int32_t count,
                                                    int32_t reset) {
   State* st = a.st;
-  const uint32_t gsz = gridDim.x * PB;
-  const uint32_t gid = blockIdx.x * PB + threadIdx.x;
-  for (int32_t k = 0; k < count; ++k) {
-    const int32_t qi = list[k];
-    const Query Q = a.q[qi];
-    const uint32_t s0 = (uint32_t)Q.slot0, src = (uint32_t)Q.src;
-    for (uint32_t v = gid; v < (uint32_t)Q.n; v += gsz) {
-      if (P == PROB_BFS) {
-        a.level[s0 + v] = (v == src) ? 0 : -1;
-      } else {
-        const uint32_t d = (v == src) ? 0u : 0xFFFFFFFFu;
-        a.dist[s0 + v] = d;
-        a.dist2[s0 + v] = d;
-        a.visit[s0 + v] = 0u;
-      }
+  const int32_t* pre = list + count;
+  // query of this workgroup: largest k with pre[k] <= blockIdx.x
+  int32_t lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= (int32_t)blockIdx.x) lo = mid; else hi = mid;
+  }
+  const int32_t qi = list[lo];
+  const uint32_t j = blockIdx.x - (uint32_t)pre[lo];
+  const uint32_t stride = (uint32_t)(pre[lo + 1] - pre[lo]) * PB;
+  const Query Q = a.q[qi];
+  const uint32_t s0 = (uint32_t)Q.slot0, src = (uint32_t)Q.src;
+  for (uint32_t v = j * PB + threadIdx.x; v < (uint32_t)Q.n; v += stride) {
+    if (P == PROB_BFS) {
+      a.level[s0 + v] = (v == src) ? 0 : -1;
+    } else {
+      const uint32_t d = (v == src) ? 0u : 0xFFFFFFFFu;
+      a.dist[s0 + v] = d;
+      a.dist2[s0 + v] = d;
+      a.visit[s0 + v] = 0u;
     }
-    const uint32_t words = ((uint32_t)Q.n + 31) / 32;
-    for (uint32_t i = gid; i < words; i += gsz) {
-      a.qmap[s0 / 32 + i] = qi;
-      if (P == PROB_BFS) {
-        const uint32_t x = (i == src >> 5) ? (1u << (src & 31)) : 0u;
-        a.visit[s0 / 32 + i] = x;  // both bitmaps hold the source
-        a.visit[(size_t)a.vwords + s0 / 32 + i] = x;
-      }
+  }
+  const uint32_t words = ((uint32_t)Q.n + 31) / 32;
+  for (uint32_t i = j * PB + threadIdx.x; i < words; i += stride) {
+    a.qmap[s0 / 32 + i] = qi;
+    if (P == PROB_BFS) {
+      const uint32_t x = (i == src >> 5) ? (1u << (src & 31)) : 0u;
+      a.visit[s0 / 32 + i] = x;  // both bitmaps hold the source
+      a.visit[(size_t)a.vwords + s0 / 32 + i] = x;
     }
   }
   if (reset) {
+    const uint32_t gsz = gridDim.x * PB;
+    const uint32_t gid = blockIdx.x * PB + threadIdx.x;
     uint32_t* sw = (uint32_t*)&st->set[0];
     for (uint32_t i = gid; i < 3 * sizeof(LevelSet) / 4; i += gsz) sw[i] = 0;
     for (uint32_t i = gid; i < 3u * (uint32_t)a.ngroups_cap; i += gsz) {
