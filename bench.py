@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
     p.add_argument("--threshold", type=int, default=None)
     p.add_argument("--coarsen", type=int, default=None)
+    p.add_argument("--split-min", type=int, default=None,
+                   help="frontier size from which a level uses two visited copies")
     p.add_argument("--agg", default=None, help="none|wave|block|<k>-block")
     p.add_argument("--sweep", action="store_true",
                    help="threshold x coarsening x granularity sweep of the workload instead")
@@ -79,7 +81,7 @@ def agg_of(s):
 TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
-         "sssp21": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4)}
+         "sssp21": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
 
 
 class Workload:
@@ -343,6 +345,8 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
         tuned["threshold"] = args.threshold
     if overrides and args.coarsen is not None:
         tuned["coarsen"] = args.coarsen
+    if overrides and args.split_min is not None:
+        tuned["split_min"] = args.split_min
     a = agg_of(args.agg) if overrides else None
     if a:
         tuned["agg"], tuned["agg_blocks"] = a
