@@ -149,21 +149,54 @@ def measure(dpo, torch, wl, dg, opts, steps, warmup, sources=None):
     return per_call, wall
 
 
+def certify(g, kind, src, out):
+    """Edge certificates of one result (no oracle): BFS (i) level[s] = 0,
+    (ii) every reached v != s has an in-neighbour one level lower, (iii) every
+    edge from a reached u reaches v with level[v] <= level[u] + 1; SSSP the same
+    with dist and w (>= 1).  Together they fix levels / distances exactly."""
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    u = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(rp))
+    v = np.asarray(g.col_idx, dtype=np.int32)
+    if kind == "bfs":
+        x = out.astype(np.int64)
+        unreached, step = -1, 1
+    else:
+        x = out.astype(np.int64) & 0xFFFFFFFF
+        unreached, step = 0xFFFFFFFF, np.asarray(g.weights, dtype=np.int64)
+    if x[src] != 0:
+        return False
+    xu, xv = x[u], x[v]
+    ru = xu != unreached
+    bound = xu + step
+    if np.any(ru & ((xv == unreached) | (xv > bound))):
+        return False
+    tight = np.zeros(g.n, dtype=bool)
+    tight[v[ru & (xv == bound)]] = True
+    need = x != unreached
+    need[src] = False
+    return bool(np.all(tight[need]))
+
+
 def reached_stats(dpo, torch, wl, dg, opts):
-    """(m_r, n_r, levels) per source, from one untimed run with counters."""
+    """(m_r, n_r, stats) per source from one untimed run with counters, and
+    whether the first source's result passes its edge certificates."""
     out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
     ws = dpo.alloc_workspace(dg, opts)
     deg = np.diff(wl.g.row_ptr).astype(np.int64)
-    res = []
+    res, ok = [], None
     for s in wl.sources:
         if wl.kind == "bfs":
             st = dpo.dpo_bfs(dg, int(s), opts, out, ws, stats=True)
-            reached = out.cpu().numpy() >= 0
+            host = out.cpu().numpy()
+            reached = host >= 0
         else:
             st = dpo.dpo_sssp(dg, int(s), opts, out, ws, stats=True)
+            host = out.cpu().numpy()
             reached = dpo.as_uint32(out) != 0xFFFFFFFF
+        if ok is None:
+            ok = certify(wl.g, wl.kind, int(s), host)
         res.append((int(deg[reached].sum()), int(reached.sum()), st))
-    return res
+    return res, ok
 
 
 KERNEL_SOURCES = ["paper_2201_02789_amd/csrc/dpo_kernels.hip",
@@ -357,7 +390,9 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
         return None
 
     # untimed run with counters: edges reached and level count per source
-    rs = reached_stats(dpo, torch, wl, dg, opts)
+    rs, certified = reached_stats(dpo, torch, wl, dg, opts)
+    if not certified:
+        log(f"[bench] ERROR: the result of source {int(wl.sources[0])} fails its edge certificates")
     levels = max(r[2]["levels"] for r in rs)
     opts.steps_per_replay = levels + 1  # one replay covers a traversal
     m_r = np.array([r[0] for r in rs], dtype=np.float64)
@@ -423,6 +458,10 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
                    "gteps_convention": "undirected edges in the reached component / time, "
                                        "summed over sources",
                    "directed_edges_per_s": round(2 * gteps * 1e9),
+                   "ms_per_traversal_mean": round(float(per_call.mean()), 4),
+                   "ms_per_traversal_median": round(float(np.median(per_call)), 4),
+                   "verified": (f"edge certificates of source {int(wl.sources[0])}'s result "
+                                f"({'pass' if certified else 'FAIL'}), untimed run"),
                    # edges the traversal actually relaxes per reached directed edge
                    # (1 for BFS; above 1 for the frontier Bellman-Ford of SSSP)
                    "work_efficiency": round(float(np.mean(
@@ -703,7 +742,7 @@ def sweep(dpo, torch, wl, dg):
     """Sweep of T x CF x granularity (and the aggregation threshold), plus flat
     and naive, on the workload's graph and sources (JSON lines)."""
     import itertools
-    rs = reached_stats(dpo, torch, wl, dg, dpo.Options())
+    rs, _ = reached_stats(dpo, torch, wl, dg, dpo.Options())
     edges = float(sum(r[0] for r in rs) / 2)
     steps = max(r[2]["levels"] for r in rs) + 1
     grid = [dpo.Options.flat(), dpo.Options.naive()]
