@@ -196,6 +196,37 @@ def test_csr_arrays_not_16_byte_aligned(s14p):
         assert np.array_equal(got_d, oracle.dijkstra(g, s)), opts.label()
 
 
+def test_raw_directed_csr_with_duplicates_and_self_loops():
+    """A CSR as a caller might pass it: directed (no symmetry), unsorted rows,
+    duplicate edges with different weights, self loops, hubs.  Only out-edges
+    are followed, by the kernels and by the oracle alike."""
+    rng = np.random.default_rng(123)
+    n = 3000
+    src = np.concatenate([rng.integers(0, n, 24000), rng.integers(0, 40, 6000)])  # hubs 0..39
+    dst = rng.integers(0, n, src.size)
+    dup = rng.integers(0, src.size, 3000)
+    src = np.concatenate([src, src[dup], np.arange(0, n, 7)])            # duplicates, self loops
+    dst = np.concatenate([dst, dst[dup], np.arange(0, n, 7)])
+    w = rng.integers(1, 256, src.size).astype(np.uint32)
+    perm_in_rows = rng.permutation(src.size)
+    order = perm_in_rows[np.argsort(src[perm_in_rows], kind="stable")]  # rows unsorted inside
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, src + 1, 1)
+    g = gg.Graph(row_ptr=np.cumsum(rp).astype(np.int32), col_idx=dst[order].astype(np.int32),
+                 weights=w[order])
+    dg = dpo.DeviceGraph.from_host(g)
+    for s in (0, 5, 2999):
+        want_l = oracle.bfs(g, s)[0]
+        want_d = oracle.dijkstra(g, s)
+        for opts in (dpo.Options(threshold=16, coarsen=2), dpo.Options.naive(), dpo.Options.flat(),
+                     dpo.Options(threshold=64, coarsen=1, split_min=0)):
+            print("raw csr", s, opts.label(), flush=True)
+            got, _ = run_bfs(dg, s, opts)
+            assert np.array_equal(got, want_l), (s, opts.label())
+            got_d, _ = run_sssp(dg, s, opts)
+            assert np.array_equal(got_d, want_d), (s, opts.label())
+
+
 def test_sssp_sweep_s14(s14p):
     g, dg = s14p
     src = gg.max_degree_vertex(g)
