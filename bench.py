@@ -336,10 +336,6 @@ def summarize_profiles(args, d):
                "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
                "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
                "traversals": trav_pmc, "launches_per_traversal": launches_per}
-    out_json = os.path.join(ROOT, "profiles", f"{args.workload}_traffic.json")
-    with open(out_json, "w") as f:
-        json.dump(traffic, f, indent=1)
-        f.write("\n")
 
     alg = line["roofline"]["algorithmic_bytes_per_launch"]
     top = sorted(stats.items(), key=lambda kv: -kv[1][1])[:8]
@@ -361,6 +357,35 @@ def summarize_profiles(args, d):
            f"write {write_b / 1e6:.2f} MB, total **{(fetch_b + write_b) / 1e6:.2f} MB** "
            f"vs algorithmic {alg / 1e6:.2f} MB ({(fetch_b + write_b) / alg:.2f}x).", "",
            f"kernel_sources_sha256 `{traffic['kernel_sources_sha256']}`", ""]
+    l2 = os.path.join(d, "l2")
+    if os.path.isdir(l2):
+        # L2 requests of the child kernel (counter run of its own; TCC_* summed
+        # over the 16 channels of each XCD and over the XCDs)
+        rows = _csv(l2, "counter_collection.csv")
+        disp = {}
+        for r in rows:
+            n = _short(r["Kernel_Name"])
+            if not n.startswith("child_kernel"):
+                continue
+            e = disp.setdefault(r["Dispatch_Id"], {"ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+        big = sorted(disp.values(), key=lambda e: -e["ns"])[:max(1, len(disp) // 16)]
+        req = sum(e.get("TCC_REQ_sum", 0) for e in big)
+        hit = sum(e.get("TCC_HIT_sum", 0) for e in big)
+        miss = sum(e.get("TCC_MISS_sum", 0) for e in big)
+        ns = sum(e["ns"] for e in big)
+        md += ["## L2 requests of the child kernel (`rocprofv3 --pmc TCC_REQ_sum TCC_HIT_sum "
+               "TCC_MISS_sum`)", "",
+               f"Longest {len(big)} of {len(disp)} child dispatches: {req / 1e6:.1f} M L2 requests, "
+               f"hit rate {hit / max(hit + miss, 1):.3f}, over {ns / 1e6:.3f} ms (durations "
+               f"of the counter run): **{req / ns:.1f} G requests/s**, against about 265 G/s measured "
+               f"for random 4-byte loads from a 512 KB table (one request per L2 channel "
+               f"and clock).", ""]
+        traffic["l2_requests_per_s"] = round(req / ns * 1e9)
+    out_json = os.path.join(ROOT, "profiles", f"{args.workload}_traffic.json")
+    with open(out_json, "w") as f:
+        json.dump(traffic, f, indent=1)
+        f.write("\n")
     out_md = os.path.join(ROOT, "profiles", f"{args.workload}_kernels.md")
     with open(out_md, "w") as f:
         f.write("\n".join(md))
