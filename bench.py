@@ -35,7 +35,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="bfs22",
-                   choices=["bfs22", "er22", "sssp21", "bfs12", "batch", "serve", "road"])
+                   choices=["bfs22", "bfs25", "er22", "sssp21", "bfs12", "batch", "serve", "road"])
     p.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
     p.add_argument("--serve-seconds", type=float, default=0.5)
     p.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
@@ -80,6 +80,7 @@ def agg_of(s):
 # MI355X; overridable from the command line.
 TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4),
+         "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
 
@@ -94,6 +95,12 @@ class Workload:
             self.sources = gg.sample_sources(self.g, 16, 1)
             self.kind = "bfs"
             self.desc = "BFS, R-MAT scale 22, edgefactor 16, a/b/c/d .57/.19/.19/.05, permuted, 16 sources"
+        elif name == "bfs25":
+            # the largest R-MAT whose directed entry count fits int32 CSR indices
+            self.g = gg.rmat(25, 16, 25, perm_seed=26)
+            self.sources = gg.sample_sources(self.g, 4, 1)
+            self.kind = "bfs"
+            self.desc = "BFS, R-MAT scale 25, edgefactor 16, permuted, 4 sources"
         elif name == "er22":
             # Erdos-Renyi control: same n and the same number of undirected edges as
             # the s22 R-MAT graph, Poisson degrees instead of a power law
