@@ -91,3 +91,55 @@ def test_engine_rejects_oversized_and_bad_queries(resident):
         eng.submit(0, graphs[0].n, o)
     assert e.value.status == dpo.DPO_ERR_SOURCE
     eng.close()
+
+
+@pytest.mark.slow
+def test_engines_at_the_serving_shape():
+    """The serving workload's shape: 8 resident weighted R-MAT graphs (scales
+    14..20 and a second 20), a BFS engine and an SSSP engine on two streams
+    stepping together, queries arriving in waves while others run.  Every
+    result equals the same query run alone; a sample also equals the oracle."""
+    graphs = [gg.add_weights(gg.rmat(sc, 16, 3000 + i, perm_seed=9000 + i), 5000 + i)
+              for i, sc in enumerate([14, 15, 16, 17, 18, 19, 20, 20])]
+    arena, vbase = gg.pack_arena(graphs)
+    da = dpo.DeviceArena(arena, vbase)
+    opts = [dpo.Options(threshold=32, coarsen=1, steps_per_replay=4)]
+    streams = {k: torch.cuda.Stream() for k in ("bfs", "sssp")}
+    engines = {k: dpo.Engine(da, k, opts, max_queries=64, max_slots=1 << 23, stream=streams[k])
+               for k in ("bfs", "sssp")}
+    rng = np.random.default_rng(21)
+    reqs = []
+    for _ in range(72):
+        kind = "bfs" if rng.random() < 0.7 else "sssp"
+        g = int(rng.integers(0, len(graphs)))
+        reqs.append((kind, g, int(gg.sample_sources(graphs[g], 1, int(rng.integers(1 << 30)))[0])))
+    outs, done = {}, set()
+    pending = list(reqs)
+    import time
+    t_end = time.time() + 120
+    while time.time() < t_end:
+        for kind, g, s in pending[:6]:
+            o = torch.full((graphs[g].n,), -9, dtype=torch.int32, device="cuda")
+            outs[(kind, engines[kind].submit(g, s, o))] = (kind, g, s, o)
+        pending = pending[6:]
+        busy = 0
+        for kind, e in engines.items():
+            run, pend = e.step()
+            busy += run + pend
+            done.update((kind, t) for t in e.poll())
+        if not pending and busy == 0:
+            break
+    for kind, e in engines.items():
+        done.update((kind, t) for t in e.poll())
+        e.close()
+    torch.cuda.synchronize()
+    assert done == set(outs), "every submitted query completes"
+    dgs = {}
+    for i, (key, (kind, g, s, o)) in enumerate(outs.items()):
+        dg = dgs.setdefault(g, dpo.DeviceGraph.from_host(graphs[g]))
+        lone, _ = (dpo.bfs if kind == "bfs" else dpo.sssp)(dg, s, opts[0])
+        assert np.array_equal(lone.cpu().numpy(), o.cpu().numpy()), (kind, g, s)
+        if i % 9 == 0:
+            want = oracle.bfs(graphs[g], s)[0] if kind == "bfs" else oracle.dijkstra(graphs[g], s)
+            got = o.cpu().numpy() if kind == "bfs" else dpo.as_uint32(o)
+            assert np.array_equal(got, want), (kind, g, s)
