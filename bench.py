@@ -82,7 +82,7 @@ TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4),
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
-         "sssp21": dict(threshold=32, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
+         "sssp21": dict(threshold=128, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
 
 
 class Workload:
@@ -753,6 +753,9 @@ def bench_road(args, dpo, torch):
                      "max_degree": int(deg.max())}}
     cfgs = {"flat": dpo.Options.flat(),
             "nested_T_above_max": dpo.Options(threshold=int(deg.max()) + 1, coarsen=1),
+            # each serialised child in its parent's lane, as in the paper
+            "nested_T_above_max_lane": dpo.Options(threshold=int(deg.max()) + 1, coarsen=1,
+                                                   serial_wave=0),
             "nested_T0_4block": dpo.Options(threshold=0, coarsen=1),
             "naive": dpo.Options.naive()}
     for name, o in cfgs.items():

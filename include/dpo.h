@@ -90,6 +90,12 @@ typedef struct {
                                and sends its atomics to a second copy; narrower
                                levels use one copy.  Affects speed only.  Default
                                65536; 0 = always two copies.                      */
+  int32_t serial_wave;      /* 1 (default): the thresholded children of a wave's
+                               parents run together, their edges 64 at a time
+                               (no launch, as Sec. III-B asks, but every lane
+                               busy); 0: each runs sequentially in its parent's
+                               lane, the paper's literal form.  The flat mode
+                               always uses the literal form.  Speed only.        */
 } dpo_options;
 
 typedef struct {

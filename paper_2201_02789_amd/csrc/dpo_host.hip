@@ -102,6 +102,7 @@ dpo_status check_options(const dpo_options& o) {
   if (o.agg < DPO_AGG_NONE || o.agg > DPO_AGG_GRID) return DPO_ERR_ARG;
   if (o.agg_threshold < 0) return DPO_ERR_ARG;
   if (o.split_min < 0) return DPO_ERR_ARG;
+  if (o.serial_wave != 0 && o.serial_wave != 1) return DPO_ERR_ARG;
   if (o.agg == DPO_AGG_MULTIBLOCK && (o.agg_blocks < 2 || o.agg_blocks > 1024)) return DPO_ERR_ARG;
   if (o.child_block != 64 && o.child_block != 128 && o.child_block != 256) return DPO_ERR_ARG;
   if (o.steps_per_replay < 0 || o.steps_per_replay > 1024) return DPO_ERR_ARG;
@@ -304,6 +305,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.k = (gran == AGG_MULTI) ? (int32_t)group_blocks(o, slots) : 1;
   a.agg_threshold = o.agg_threshold;
   a.split_min = o.split_min;
+  a.serial_wave = o.serial_wave;
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
@@ -813,6 +815,7 @@ void dpo_default_options(dpo_options* o) {
   o->steps_per_replay = 0;
   o->agg_threshold = 0;
   o->split_min = 65536;
+  o->serial_wave = 1;
 }
 
 size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o) {

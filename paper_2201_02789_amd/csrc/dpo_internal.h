@@ -94,6 +94,9 @@ struct Args {
   int32_t vwords;                  // words of one BFS bitmap (slots / 32)
   int32_t split_min;               // frontier size from which a level probes one
                                    // visited copy and updates the other
+  int32_t serial_wave;             // thresholded children: run by the wave together
+                                   // (1) or each in its parent's lane (0)
+  int32_t pad2;
 };
 
 const void* parent_kernel_ptr(int problem, int gran);

@@ -402,6 +402,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ unsigned long long s_stats[NSTAT];
   __shared__ uint32_t s_live[MAX_QUERIES / 32];  // queries seen at this level
   __shared__ uint32_t s_ser[2];                  // serial list: length, next entry
+  __shared__ uint32_t s_soff[NW][64];            // per wave: scanned child sizes of a group
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
@@ -634,51 +635,120 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     }
   }
 
-  // ---- pass 2: thresholded children run serially, each by one lane
-  // (Sec. III-B).  A lane whose child is done takes the next parent of the
-  // list, so lanes do not idle until the wave's largest child finishes.
+  // ---- pass 2: the thresholded children (Sec. III-B: no launch; the parent's
+  // own threads run the child work).
   __syncthreads();
   {
     const uint32_t nser = s_ser[0];
     if (tid == 0) s_ser[1] = 0;  // next list entry
     __syncthreads();
     constexpr int U = 8;
-    while (true) {
-      const bool idle = e >= end;
-      const unsigned long long m = __ballot(idle);
-      uint32_t base = 0;
-      if (m) {
-        if (lane == __builtin_ctzll(m)) base = atomicAdd(&s_ser[1], (uint32_t)__popcll(m));
-        base = __shfl(base, __builtin_ctzll(m), 64);
-      }
-      if (idle) {
-        const uint32_t k = base + lane_rank(m);
-        if (k < nser) {
-          const int4 r = a.ser[(size_t)(blockIdx.x + (k / PB) * gridDim.x) * PB + k % PB];
-          const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
-          e = r.x;
-          end = r.x + r.y;
-          ctx.vbase = Q.vbase;
-          ctx.n = Q.n;
-          ctx.sbase = Q.slot0 - Q.vbase;
-          ctx.lv = (int32_t)(L + 1) - Q.lstart;
-          ctx.du = (uint32_t)r.w;
+    if (G != AGG_FLAT && a.serial_wave) {
+      // The wave runs the children of up to 64 parents together: their edges
+      // are concatenated (a wave scan of the degrees) and taken 64 at a time,
+      // each lane finding its parent by a search of the scanned offsets, so
+      // lanes read consecutive edges and none idles while a long child runs.
+      uint32_t* off = s_soff[wave];
+      bool first = true;
+      while (true) {
+        int32_t cs = 0, cd = 0;
+        Elem cc{0, 0, 0, 0, 0u};
+        if (in_regs) {  // the lanes' own parents from pass 1: one group
+          if (!first) break;
+          cs = e;
+          cd = end - e;
+          cc = ctx;
+        } else {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&s_ser[1], 64u);
+          base = __shfl(base, 0, 64);
+          if (base >= nser) break;
+          const uint32_t k = base + (uint32_t)lane;
+          if (k < nser) {
+            const int4 r = a.ser[(size_t)(blockIdx.x + (k / PB) * gridDim.x) * PB + k % PB];
+            const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
+            cs = r.x;
+            cd = r.y;
+            cc = Elem{Q.vbase, Q.n, Q.slot0 - Q.vbase, (int32_t)(L + 1) - Q.lstart, (uint32_t)r.w};
+          }
         }
-      }
-      if (!__any(e < end)) break;
-      int32_t v[U], out[U];
-      uint32_t w[U];
-      Elem c[U];
+        first = false;
+        const uint32_t incl = wave_incl_scan((uint32_t)cd, lane);
+        const uint32_t excl = incl - (uint32_t)cd;
+        const uint32_t total = __shfl(incl, 63, 64);
+        wave_lds_sync();
+        off[lane] = excl;
+        wave_lds_sync();
+        for (uint32_t x0 = 0; x0 < total; x0 += 64u * U) {
+          int32_t v[U], out[U];
+          uint32_t w[U];
+          Elem c[U];
 #pragma unroll
-      for (int r = 0; r < U; ++r) {
-        v[r] = (e + r < end) ? a.col[e + r] : -1;
-        w[r] = (P == PROB_SSSP && e + r < end) ? a.w[e + r] : 0u;
-        c[r] = ctx;
-      }
-      visit_batch<P, U>(a, vis, v, w, c, L, out);
+          for (int u = 0; u < U; ++u) {
+            const uint32_t x = x0 + (uint32_t)u * 64u + (uint32_t)lane;
+            const uint32_t xs = x < total ? x : total - 1;
+            // parent of edge xs: the last lane whose offset is <= xs
+            uint32_t pl = 0;
 #pragma unroll
-      for (int r = 0; r < U; ++r) stage_push(s, out[r] >= 0, out[r], a, cur, fout, lane);
-      e = min(e + U, end);
+            for (uint32_t st = 32; st; st >>= 1)
+              if (off[pl + st] <= xs) pl += st;
+            const int32_t sp = __shfl(cs, (int)pl, 64);
+            const uint32_t ep = (uint32_t)__shfl((int32_t)excl, (int)pl, 64);
+            c[u] = Elem{__shfl(cc.vbase, (int)pl, 64), __shfl(cc.n, (int)pl, 64),
+                        __shfl(cc.sbase, (int)pl, 64), __shfl(cc.lv, (int)pl, 64),
+                        (uint32_t)__shfl((int32_t)cc.du, (int)pl, 64)};
+            const int32_t ei = sp + (int32_t)(xs - ep);
+            v[u] = x < total ? a.col[ei] : -1;
+            w[u] = (P == PROB_SSSP && x < total) ? a.w[ei] : 0u;
+          }
+          visit_batch<P, U>(a, vis, v, w, c, L, out);
+#pragma unroll
+          for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
+        }
+        wave_lds_sync();  // off[] is rewritten by the next group
+      }
+    } else {
+      // Each child runs sequentially in one lane (the paper's form; always
+      // used by the flat kernel).  A lane whose child is done takes the next
+      // parent of the list, so lanes do not idle until the wave's largest
+      // child finishes.
+      while (true) {
+        const bool idle = e >= end;
+        const unsigned long long m = __ballot(idle);
+        uint32_t base = 0;
+        if (m) {
+          if (lane == __builtin_ctzll(m)) base = atomicAdd(&s_ser[1], (uint32_t)__popcll(m));
+          base = __shfl(base, __builtin_ctzll(m), 64);
+        }
+        if (idle) {
+          const uint32_t k = base + lane_rank(m);
+          if (k < nser) {
+            const int4 r = a.ser[(size_t)(blockIdx.x + (k / PB) * gridDim.x) * PB + k % PB];
+            const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
+            e = r.x;
+            end = r.x + r.y;
+            ctx.vbase = Q.vbase;
+            ctx.n = Q.n;
+            ctx.sbase = Q.slot0 - Q.vbase;
+            ctx.lv = (int32_t)(L + 1) - Q.lstart;
+            ctx.du = (uint32_t)r.w;
+          }
+        }
+        if (!__any(e < end)) break;
+        int32_t v[U], out[U];
+        uint32_t w[U];
+        Elem c[U];
+#pragma unroll
+        for (int r = 0; r < U; ++r) {
+          v[r] = (e + r < end) ? a.col[e + r] : -1;
+          w[r] = (P == PROB_SSSP && e + r < end) ? a.w[e + r] : 0u;
+          c[r] = ctx;
+        }
+        visit_batch<P, U>(a, vis, v, w, c, L, out);
+#pragma unroll
+        for (int r = 0; r < U; ++r) stage_push(s, out[r] >= 0, out[r], a, cur, fout, lane);
+        e = min(e + U, end);
+      }
     }
   }
   if (word_fold) {

@@ -47,7 +47,7 @@ class _Options(ctypes.Structure):
                 ("coarsen", ctypes.c_int32), ("agg", ctypes.c_int32),
                 ("agg_blocks", ctypes.c_int32), ("child_block", ctypes.c_int32),
                 ("steps_per_replay", ctypes.c_int32), ("agg_threshold", ctypes.c_int32),
-                ("split_min", ctypes.c_int32)]
+                ("split_min", ctypes.c_int32), ("serial_wave", ctypes.c_int32)]
 
 
 class _Csr(ctypes.Structure):
@@ -84,6 +84,7 @@ class Options:
     steps_per_replay: int = 0
     agg_threshold: int = 0
     split_min: int = 65536
+    serial_wave: int = 1
 
     def c(self) -> _Options:
         return _Options(*(int(getattr(self, f.name)) for f in fields(self)))
@@ -106,7 +107,8 @@ class Options:
         g = {0: "none", 1: "wave", 2: "block", 3: f"{self.agg_blocks}-block", 4: "grid"}[self.agg]
         at = f"-A{self.agg_threshold}" if self.agg_threshold else ""
         sm = f"-S{self.split_min}" if self.split_min != 65536 else ""
-        return f"T{self.threshold}-CF{self.coarsen}-{g}{at}{sm}"
+        sl = "-lane" if not self.serial_wave else ""
+        return f"T{self.threshold}-CF{self.coarsen}-{g}{at}{sm}{sl}"
 
 
 _lib = None

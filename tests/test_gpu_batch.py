@@ -55,7 +55,7 @@ def run_batch(kind, da, qs, bopts, stats=False):
 MODES = [dict(), dict(agg=dpo.DPO_AGG_WAVE), dict(agg=dpo.DPO_AGG_BLOCK),
          dict(agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=16), dict(agg=dpo.DPO_AGG_NONE),
          dict(mode=dpo.DPO_MODE_FLAT), dict(child_block=64, steps_per_replay=2),
-         dict(split_min=0), dict(split_min=256, steps_per_replay=3)]
+         dict(split_min=0), dict(split_min=256, steps_per_replay=3), dict(serial_wave=0)]
 
 
 @pytest.mark.parametrize("common", MODES, ids=[str(m) for m in MODES])

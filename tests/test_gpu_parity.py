@@ -227,6 +227,27 @@ def test_raw_directed_csr_with_duplicates_and_self_loops():
             assert np.array_equal(got_d, want_d), (s, opts.label())
 
 
+@pytest.mark.parametrize("serial_wave", [0, 1], ids=["lane", "wave"])
+def test_serial_children_lane_and_wave_forms(s14p, serial_wave):
+    """Thresholded children run in their parent's lane (the paper's form) or
+    by the parent's wave together: same levels, distances and counters, for
+    thresholds that send few, most or all children down the serial path."""
+    g, dg = s14p
+    srcs = [int(x) for x in gg.sample_sources(g, 2, 3)] + [gg.max_degree_vertex(g)]
+    for T in (2, 16, 64, 100000):
+        for agg, k in ((dpo.DPO_AGG_BLOCK, 4), (dpo.DPO_AGG_MULTIBLOCK, 4)):
+            opts = dpo.Options(threshold=T, coarsen=1, agg=agg, agg_blocks=k, serial_wave=serial_wave)
+            ws = dpo.alloc_workspace(dg, opts)
+            for s in srcs:
+                print("serial", opts.label(), s, flush=True)
+                want = oracle.bfs(g, s)[0]
+                got, st = run_bfs(dg, s, opts, ws=ws)
+                assert np.array_equal(got, want), (opts.label(), s)
+                check_bfs_stats(g, want, opts, st)
+                got_d, _ = run_sssp(dg, s, opts, ws=ws)
+                assert np.array_equal(got_d, oracle.dijkstra(g, s)), (opts.label(), s)
+
+
 def test_sssp_sweep_s14(s14p):
     g, dg = s14p
     src = gg.max_degree_vertex(g)
