@@ -85,6 +85,9 @@ TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=128, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
 
 
+SERVE_T = 64  # threshold of the serving engines (swept: 32, 64, 128)
+
+
 class Workload:
     def __init__(self, name):
         from paper_2201_02789_amd import graphgen as gg
@@ -676,8 +679,8 @@ def bench_serve(args, dpo, torch, full_line=False):
     da = dpo.DeviceArena(arena, vbase)
     pools = [gg.sample_sources(g, 64, 6000 + i) for i, g in enumerate(graphs)]
     log(f"[serve] graphs ready, arena n={arena.n} m={arena.m} ({time.time() - t0:.1f}s)")
-    opts = [dpo.Options(threshold=32, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
-                        steps_per_replay=4)]
+    opts = [dpo.Options(threshold=args.threshold if args.threshold is not None else SERVE_T,
+                        coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4, steps_per_replay=4)]
     s_bfs, s_sssp = torch.cuda.Stream(), torch.cuda.Stream()
     max_slots = 1 << 24
     engines = {"bfs": dpo.Engine(da, "bfs", opts, max_queries=256, max_slots=max_slots,
