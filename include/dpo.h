@@ -103,7 +103,7 @@ typedef struct {
   int32_t m;                /* directed CSR entries, >= 0                          */
   const int32_t* row_ptr;   /* device, int32[n + 1], row_ptr[0] = 0, row_ptr[n] = m */
   const int32_t* col_idx;   /* device, int32[m], each in [0, n)                     */
-  const uint32_t* weights;  /* device, uint32[m] >= 1 (SSSP only; NULL for BFS)     */
+  const uint32_t* weights;  /* device, uint32[m] (SSSP only; NULL for BFS)          */
 } dpo_csr;
 
 /* Per-traversal counters (host struct).  Requesting them makes the kernels
@@ -144,10 +144,11 @@ dpo_status dpo_bfs(const dpo_csr* g, int32_t source, const dpo_options* o, int32
                    void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
 
 /* Single-source shortest paths (Table I, SSSP) by frontier Bellman-Ford with
- * atomicMin relaxations.  g->weights required, each >= 1; n must be at most
- * 16,843,009 so that every finite distance fits below 0xFFFFFFFF.
+ * atomicMin relaxations.  g->weights required, any uint32 values (0 allowed).
+ * Path sums saturate at 0xFFFFFFFF instead of wrapping.
  * dist: device uint32[g->n]; on return the exact shortest distances,
- * 0xFFFFFFFF if unreachable.  Other arguments as for dpo_bfs. */
+ * 0xFFFFFFFF if unreachable (and for a vertex whose shortest distance is
+ * 0xFFFFFFFF or more).  Other arguments as for dpo_bfs. */
 dpo_status dpo_sssp(const dpo_csr* g, int32_t source, const dpo_options* o, uint32_t* dist,
                     void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
 

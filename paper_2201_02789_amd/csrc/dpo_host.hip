@@ -437,7 +437,6 @@ dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_opt
   if (s != DPO_OK) return s;
   s = check_options(*o);
   if (s != DPO_OK) return s;
-  if (problem == PROB_SSSP && g->n > 16843009) return DPO_ERR_ARG;
   if (source < 0 || source >= g->n) return DPO_ERR_SOURCE;
   if (ws_bytes < layout_for(round32(g->n), 1, *o).total) return DPO_ERR_WORKSPACE;
   Runtime& r = rt();
@@ -489,7 +488,6 @@ dpo_status traverse_batch(int problem, const dpo_arena* ar, const dpo_query* qs,
   if (s != DPO_OK) return s;
   for (int32_t b = 0; b < nb; ++b)
     if ((s = check_options(bopts[b])) != DPO_OK) return s;
-  if (problem == PROB_SSSP && ar->csr.n > 16843009) return DPO_ERR_ARG;
   const int64_t slots = batch_slots(ar, qs, nq, nullptr);
   if (slots < 0) return DPO_ERR_ARG;
   for (int32_t i = 0; i < nq; ++i) {
@@ -703,7 +701,6 @@ dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_opt
     if ((s = check_options(bucket_opts[b])) != DPO_OK) return s;
   if (max_queries < 1 || max_queries > MAX_QUERIES || max_slots < 32 || max_slots > INT32_MAX)
     return DPO_ERR_ARG;
-  if (problem == PROB_SSSP && arena->csr.n > 16843009) return DPO_ERR_ARG;
   max_slots = round32(max_slots);
   if (ws_bytes < layout_for(max_slots, max_queries, bucket_opts[0]).total) return DPO_ERR_WORKSPACE;
   if (graph_bucket)

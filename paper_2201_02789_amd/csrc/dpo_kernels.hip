@@ -283,7 +283,10 @@ __device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const
     uint32_t nd[U], cur[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      nd[u] = c[u].du + w[u];
+      // saturating: a walk of 2^32 - 1 or more never improves a distance, so
+      // no wrapped sum can undercut the true one
+      const uint32_t sum = c[u].du + w[u];
+      nd[u] = sum < c[u].du ? 0xFFFFFFFFu : sum;
       cur[u] = sl[u] >= 0 ? dp[sl[u]] : 0u;
     }
     uint32_t ncand = 0;

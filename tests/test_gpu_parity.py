@@ -144,9 +144,9 @@ def test_visited_copies_every_mode(s14p, split_min):
             assert np.array_equal(got_d, oracle.dijkstra(g, s)), (opts.label(), s)
 
 
-def test_sssp_distances_beyond_the_bound_code():
-    """Distances from 0 up to ~10^8: small ones have exact bound codes, large
-    ones saturate to "unknown"; both must give the oracle's distances."""
+def test_sssp_large_distances():
+    """Distances from 0 up to ~10^8 on a 60 x 55 grid give the oracle's
+    distances."""
     base = gg.add_weights(gg.grid_graph(60, 55), 77)
     for scale in (1, 4099):
         g = gg.Graph(row_ptr=base.row_ptr, col_idx=base.col_idx,
@@ -157,6 +157,74 @@ def test_sssp_distances_beyond_the_bound_code():
             print("big distances", scale, opts.label(), int(want.max()), flush=True)
             got, _ = run_sssp(dg, 0, opts)
             assert np.array_equal(got, want), (scale, opts.label())
+
+
+def _directed_csr(n, src, dst, w):
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, np.asarray(src) + 1, 1)
+    order = np.argsort(src, kind="stable")
+    return gg.Graph(row_ptr=np.cumsum(rp).astype(np.int32),
+                    col_idx=np.asarray(dst)[order].astype(np.int32),
+                    weights=np.asarray(w, dtype=np.uint32)[order])
+
+
+SSSP_EDGE_OPTS = (dpo.Options(), dpo.Options(threshold=16, coarsen=2), dpo.Options.naive(),
+                  dpo.Options.flat(), dpo.Options(threshold=8, coarsen=1, split_min=0))
+
+
+@pytest.mark.parametrize("kind", ["near_2_32", "zero"])
+def test_sssp_extreme_weights(kind):
+    """Weights near 2^32 (every relaxation along them from a vertex farther
+    than 2^20 would wrap a 32-bit sum to a value below the true distance) and
+    zero weights.  A chain of modest edges keeps every shortest distance below
+    0xFFFFFFFF, so the uint64 oracle is exact."""
+    rng = np.random.default_rng(99 if kind == "zero" else 98)
+    n = 4000
+    chain = rng.permutation(n)
+    src = [chain[:-1], chain[1:]]
+    dst = [chain[1:], chain[:-1]]
+    w = [rng.integers(1, 1 << 20, n - 1)] * 2
+    r_src = np.concatenate([rng.integers(0, n, 30000), rng.integers(0, 16, 8000)])  # hubs 0..15
+    r_dst = rng.integers(0, n, r_src.size)
+    if kind == "near_2_32":
+        r_w = np.where(rng.random(r_src.size) < 0.4,
+                       (1 << 32) - rng.integers(1, 1 << 20, r_src.size),
+                       rng.integers(1 << 19, 1 << 22, r_src.size))
+    else:
+        r_w = np.where(rng.random(r_src.size) < 0.3, 0, rng.integers(1, 1 << 16, r_src.size))
+    g = _directed_csr(n, np.concatenate(src + [r_src]), np.concatenate(dst + [r_dst]),
+                      np.concatenate(w + [r_w]).astype(np.uint64).astype(np.uint32))
+    dg = dpo.DeviceGraph.from_host(g)
+    for s in (int(chain[0]), 3, int(chain[n // 2])):
+        want = oracle.dijkstra(g, s)
+        assert want.max() < 0xFFFFFFFF
+        for opts in SSSP_EDGE_OPTS:
+            print("extreme weights", kind, s, opts.label(), flush=True)
+            got, _ = run_sssp(dg, s, opts)
+            assert np.array_equal(got, want), (kind, s, opts.label())
+
+
+def test_sssp_sums_saturate_at_0xffffffff():
+    """Closed form: on a path with weights 2^31 from one end, vertex i is at
+    i * 2^31; from i = 2 on that is at least 2^32 - 1 and reads 0xFFFFFFFF, as
+    does a leaf hung on the source by a 0xFFFFFFFF edge.  A short cut of
+    weight 5 from the source to vertex 4 makes 4 and 5 finite again."""
+    n = 8
+    src = [0, 1, 2, 3, 4, 0]
+    dst = [1, 2, 3, 4, 5, 6]
+    w = [1 << 31] * 5 + [0xFFFFFFFF]
+    sat = 0xFFFFFFFF
+    g = _directed_csr(n, np.array(src), np.array(dst), np.array(w, dtype=np.uint64))
+    want = np.array([0, 1 << 31, sat, sat, sat, sat, sat, sat], dtype=np.uint32)
+    g2 = _directed_csr(n, np.array(src + [0]), np.array(dst + [4]),
+                       np.array(w + [5], dtype=np.uint64))
+    want2 = want.copy()
+    want2[4], want2[5] = 5, 5 + (1 << 31)
+    for graph, expect in ((g, want), (g2, want2)):
+        dg = dpo.DeviceGraph.from_host(graph)
+        for opts in SSSP_EDGE_OPTS:
+            got, _ = run_sssp(dg, 0, opts)
+            assert np.array_equal(got, expect), (opts.label(), got)
 
 
 def test_relabelled_graph_gives_permuted_outputs(s14p):

@@ -96,6 +96,28 @@ def test_dijkstra_exhaustive_small_weights():
                 assert np.array_equal(oracle.dijkstra(g, s), fw[s])
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_dijkstra_zero_and_near_2_32_weights_vs_floyd_warshall(seed):
+    """Weights 0 and just below 2^32 (sums past 32 bits) against
+    Floyd-Warshall in int64: exact when every distance fits below
+    0xFFFFFFFF, an error otherwise."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(3, 41))
+    edges = [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < 0.15]
+    kind = rng.integers(0, 3, size=len(edges))
+    w = np.where(kind == 0, 0, np.where(kind == 1, rng.integers(1, 1 << 20, size=len(edges)),
+                                        (1 << 32) - rng.integers(1, 1 << 20, size=len(edges))))
+    g = gg.from_edges(n, edges, w)
+    fw = floyd_warshall(n, edges, w)
+    for s in range(n):
+        finite = fw[s][fw[s] != U]
+        if finite.size and finite.max() >= U:
+            with pytest.raises(ValueError):
+                oracle.dijkstra(g, s)
+        else:
+            assert np.array_equal(oracle.dijkstra(g, s), fw[s])
+
+
 def test_unit_weights_dijkstra_equals_bfs():
     g = gg.rmat(10, 8, 3, perm_seed=5)
     g1 = gg.Graph(g.row_ptr, g.col_idx, np.ones(g.m, dtype=np.uint32))
