@@ -350,7 +350,7 @@ def summarize_profiles(args, d):
     alg = line["roofline"]["algorithmic_bytes_per_launch"]
     top = sorted(stats.items(), key=lambda kv: -kv[1][1])[:8]
     md = [f"# {args.workload}: kernel time and HBM traffic ({label})", "",
-          "Commands (repository root, MI355X, `cd /tmp && export TMPDIR=/tmp` first):", "",
+          "Commands (MI355X, from the repository root, after `export TMPDIR=/tmp`):", "",
           "```"] + [ln.rstrip() for ln in open(os.path.join(d, "commands.txt"))] + ["```", "",
           "## Kernel trace (`rocprofv3 --kernel-trace --stats`)", "",
           "| kernel | calls | total ms | mean us |", "|---|---|---|---|"]
