@@ -125,12 +125,12 @@ typedef struct {
 void dpo_default_options(dpo_options* o);
 
 /* Device workspace bytes needed by dpo_bfs / dpo_sssp on a graph with g->n
- * vertices under options o (the same buffer serves both); about 68 bytes per
+ * vertices under options o (the same buffer serves both); about 72 bytes per
  * vertex for large graphs.  0 on bad args.
  * Layout, all inside the caller's buffer: traversal state and counters, two
  * frontier buffers (64 sharded queues plus an overflow queue), a per-vertex
  * visit word (two visited bitmaps for BFS, iteration stamps for SSSP), a
- * second distance array (SSSP), launch records of 20 bytes per vertex, a list
+ * second distance array (SSSP), launch records of 24 bytes per vertex, a list
  * of thresholded parents of 16 bytes per vertex, 8 descriptor queues of 16
  * bytes per possible aggregated grid and per-workgroup counters. */
 size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o);

@@ -28,7 +28,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t state, queries, qlist, qmap, grp_packed, grp_done, front0, front1, visit, dist2, rec, rec_q,
-      ser, desc, stats, total;
+      rec_slot, ser, desc, stats, total;
   int32_t ngroups_cap, desc_cap, fcap;
 };
 
@@ -87,6 +87,7 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.dist2 = off; off = align_up(off + (size_t)slots * 4);  // SSSP second distance array
   L.rec = off; off = align_up(off + (size_t)slots * 16);
   L.rec_q = off; off = align_up(off + (size_t)slots * 4);
+  L.rec_slot = off; off = align_up(off + (size_t)slots * 4);  // SSSP
   L.ser = off; off = align_up(off + (size_t)cdiv(slots, PB) * PB * 16);
   L.desc = off; off = align_up(off + (size_t)NQD * L.desc_cap * 16);
   L.stats = off; off = align_up(off + (size_t)MAX_GRID * NSTAT * 8);
@@ -294,6 +295,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.vwords = (int32_t)cdiv(slots, 32);
   a.rec = (int4*)(base + lay.rec);
   a.rec_q = (int32_t*)(base + lay.rec_q);
+  a.rec_slot = (int32_t*)(base + lay.rec_slot);
   a.ser = (int4*)(base + lay.ser);
   a.qmap = (int32_t*)(base + lay.qmap);
   a.desc = (int4*)(base + lay.desc);

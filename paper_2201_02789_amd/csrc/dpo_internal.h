@@ -75,6 +75,7 @@ struct Args {
   uint32_t* visit;                 // BFS: two bitmaps of vwords words; SSSP: stamps [slots]
   int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
   int32_t* rec_q;                  // [slots] query of each record
+  int32_t* rec_slot;               // [slots] SSSP: slot of each record's parent
   int4* ser;                       // [slots rounded up to PB] thresholded parents
                                    // {row start, deg, slot, parent distance}
   int32_t* qmap;                   // [slots / 32] query owning each 32-slot chunk

@@ -352,6 +352,16 @@ __device__ __forceinline__ void publish(const Args& a, LevelSet* ls, uint32_t q,
   a.desc[(size_t)q * a.desc_cap + d] = make_int4((int32_t)rec_base, (int32_t)nrec, (int32_t)old, 0);
 }
 
+// Launch record `r` of the level: the parent's row, child count, scanned
+// offset of its coarsened grid and distance; its query; for SSSP its slot.
+template <int P>
+__device__ __forceinline__ void put_record(const Args& a, uint32_t r, int32_t start, int32_t deg,
+                                           uint32_t off, uint32_t du, int32_t q, int32_t slot) {
+  a.rec[r] = make_int4(start, deg, (int32_t)off, (int32_t)du);
+  a.rec_q[r] = q;
+  if (P == PROB_SSSP) a.rec_slot[r] = slot;
+}
+
 // Frontier entry i of level L: queue q with s_fpre[q] <= i < s_fpre[q + 1].
 __device__ __forceinline__ int32_t frontier_at(const Args& a, const int32_t* fin,
                                                const uint32_t* s_fpre, uint32_t i) {
@@ -503,8 +513,8 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       }
       if (ser) {
         ++cn.serial;
-        cn.eser += deg;
-        if (in_regs) {
+        if (in_regs) {  // (listed parents count their edges in pass 2)
+          cn.eser += deg;
           e = start;
           end = start + deg;
           ctx = p.e;
@@ -531,8 +541,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         // every launching parent publishes its own grid; its record sits at
         // its frontier index
         if (launch) {
-          a.rec[i] = make_int4(start, deg, 0, (int32_t)du);
-          a.rec_q[i] = q;
+          put_record<P>(a, i, start, deg, 0u, du, q, slot);
           publish(a, cur, vb % NQD, i, 1u, cg);
           ++cn.desc;
         }
@@ -543,8 +552,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         if (m && nrec < (uint32_t)a.agg_threshold) {
           // too few participants (Sec. V-B): each parent launches its own grid
           if (launch) {
-            a.rec[seg + lane_rank(m)] = make_int4(start, deg, 0, (int32_t)du);
-            a.rec_q[seg + lane_rank(m)] = q;
+            put_record<P>(a, seg + lane_rank(m), start, deg, 0u, du, q, slot);
             publish(a, cur, vb % NQD, seg + lane_rank(m), 1u, cg);
             ++cn.desc;
           }
@@ -552,8 +560,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           const uint32_t incl = wave_incl_scan(cg, lane);
           const uint32_t total = __shfl(incl, 63, 64);
           if (launch) {
-            a.rec[seg + lane_rank(m)] = make_int4(start, deg, (int32_t)(incl - cg), (int32_t)du);
-            a.rec_q[seg + lane_rank(m)] = q;
+            put_record<P>(a, seg + lane_rank(m), start, deg, incl - cg, du, q, slot);
           }
           if (lane == 0) {
             publish(a, cur, vb % NQD, seg, nrec, total);
@@ -581,17 +588,14 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           if (nrec_b < (uint32_t)a.agg_threshold) {
             // too few participants (Sec. V-B): each parent launches its own grid
             if (launch) {
-              const uint32_t slot = seg + roff + lane_rank(m);
-              a.rec[slot] = make_int4(start, deg, 0, (int32_t)du);
-              a.rec_q[slot] = q;
-              publish(a, cur, vb % NQD, slot, 1u, cg);
+              const uint32_t r = seg + roff + lane_rank(m);
+              put_record<P>(a, r, start, deg, 0u, du, q, slot);
+              publish(a, cur, vb % NQD, r, 1u, cg);
               ++cn.desc;
             }
           } else {
             if (launch) {
-              a.rec[seg + roff + lane_rank(m)] =
-                  make_int4(start, deg, (int32_t)(coff + incl - cg), (int32_t)du);
-              a.rec_q[seg + roff + lane_rank(m)] = q;
+              put_record<P>(a, seg + roff + lane_rank(m), start, deg, coff + incl - cg, du, q, slot);
             }
             if (tid == 0 && nrec_b) {
               publish(a, cur, vb % NQD, seg, nrec_b, total_b);
@@ -614,9 +618,8 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           __syncthreads();
           const uint32_t slot0 = s_bc[0], off0 = s_bc[1];
           if (launch) {
-            a.rec[seg + slot0 + roff + lane_rank(m)] =
-                make_int4(start, deg, (int32_t)(off0 + coff + incl - cg), (int32_t)du);
-            a.rec_q[seg + slot0 + roff + lane_rank(m)] = q;
+            put_record<P>(a, seg + slot0 + roff + lane_rank(m), start, deg, off0 + coff + incl - cg,
+                          du, q, slot);
           }
           if (tid == 0) {
             // the group's last block to finish "launches" the aggregated grid;
@@ -673,6 +676,9 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
             cs = r.x;
             cd = r.y;
             cc = Elem{Q.vbase, Q.n, Q.slot0 - Q.vbase, (int32_t)(L + 1) - Q.lstart, (uint32_t)r.w};
+            // SSSP: a parent lowered again during this level expands at the next
+            if (P == PROB_SSSP && coherent_load(&vis.claim[r.z]) < (uint32_t)r.w) cd = 0;
+            cn.eser += (uint32_t)cd;
           }
         }
         first = false;
@@ -730,6 +736,9 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
             const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
             e = r.x;
             end = r.x + r.y;
+            // SSSP: a parent lowered again during this level expands at the next
+            if (P == PROB_SSSP && coherent_load(&vis.claim[r.z]) < (uint32_t)r.w) end = e;
+            cn.eser += (uint32_t)(end - e);
             ctx.vbase = Q.vbase;
             ctx.n = Q.n;
             ctx.sbase = Q.slot0 - Q.vbase;
@@ -794,19 +803,32 @@ struct Window {
   uint32_t excl, nslices;           // exclusive scan of the slice counts, total
   int32_t vbase, n, sbase, lv;      // query fields (Elem)
   uint32_t du;
+  int32_t ps;                       // SSSP: the parent's slot
   bool last;                        // the wave's range ends in this window
   bool bad;
 };
 
-__device__ __forceinline__ Window load_window(const Args& a, uint32_t base, uint32_t wn,
-                                              uint32_t gbase, uint32_t t0, uint32_t t1, int lane,
-                                              uint32_t L, uint32_t& blocks, uint32_t& edges) {
-  Window w{0, 0, 0, 0u, 0u, 0, 0, 0, 0, 0u, false, false};
+// Window of the records base .. base + wn - 1.  SSSP: a parent whose distance
+// was lowered again during this level is already queued for the next level,
+// where it expands with the lower distance; every relaxation of its share here
+// would be dominated then, so the share is dropped (claim: the distance copy
+// this level's atomicMin updates).
+template <int P>
+__device__ __forceinline__ Window load_window(const Args& a, const uint32_t* claim, uint32_t base,
+                                              uint32_t wn, uint32_t gbase, uint32_t t0, uint32_t t1,
+                                              int lane, uint32_t L, uint32_t& blocks) {
+  Window w{0, 0, 0, 0u, 0u, 0, 0, 0, 0, 0u, 0, false, false};
   uint32_t ns = 0;
   bool bad = false, ends = false;
   if ((uint32_t)lane < wn) {
     const int4 rec = a.rec[base + lane];
     const int32_t q = a.rec_q[base + lane];
+    uint32_t pnow = 0xFFFFFFFFu;  // the parent's distance now (SSSP)
+    if (P == PROB_SSSP) {
+      w.ps = a.rec_slot[base + lane];
+      if ((uint32_t)w.ps < (uint32_t)a.slots) pnow = coherent_load(&claim[w.ps]);
+      else bad = true;
+    }
     int32_t CF = 1;
     if ((uint32_t)q < (uint32_t)a.nq) {
       const Query Q = a.q[q];
@@ -828,13 +850,13 @@ __device__ __forceinline__ Window load_window(const Args& a, uint32_t base, uint
       const uint32_t G = gbase + (uint32_t)rec.z;
       const uint32_t lo = max(G, t0), hi = min(G + cgr, t1);
       ends = G + cgr >= t1;
-      if (hi > lo) {
+      const bool superseded = P == PROB_SSSP && pnow < (uint32_t)rec.w;
+      if (hi > lo && !superseded) {
         w.rs = rec.x;
         w.elo = (int32_t)((lo - G) * span);
         w.ehi = min(deg, (int32_t)((hi - G) * span));
         ns = ceil_div((uint32_t)(w.ehi - w.elo), 64u);
         blocks += hi - lo;
-        edges += (uint32_t)(w.ehi - w.elo);
       }
       w.du = (uint32_t)rec.w;
     }
@@ -901,8 +923,8 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
     constexpr int U = 8;
     while (true) {
       const uint32_t wn = min(64u, (uint32_t)dd.y - r);
-      const Window win = load_window(a, (uint32_t)dd.x + r, wn, s_qpre[q] + (uint32_t)dd.z, t0, t1,
-                                     lane, L, cn.child, cn.echild);
+      const Window win = load_window<P>(a, vis.claim, (uint32_t)dd.x + r, wn,
+                                        s_qpre[q] + (uint32_t)dd.z, t0, t1, lane, L, cn.child);
       if (win.bad) {
         if (lane == 0) set_error(st, ERR_CAPACITY);
         break;
@@ -910,10 +932,19 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
       // Coarsening loop (Sec. IV-B): a coarsened block covers original blocks
       // j*CF .. j*CF+CF-1 of CB lanes, the contiguous edges [j*CF*CB,
       // (j+1)*CF*CB) of its row, taken here 64 lanes at a time.
+      // SSSP: the parents' distances are loaded again with each batch and
+      // checked at the next one (by then the load has returned), so shares of
+      // parents lowered while the wave runs them are cut short.
+      uint32_t pnow = 0xFFFFFFFFu;
       for (uint32_t x0 = 0; x0 < win.nslices; x0 += U) {
         int32_t v[U], out[U];
         uint32_t w[U];
         Elem c[U];
+        unsigned long long sup = 0ull;  // records whose parent was lowered
+        if (P == PROB_SSSP) {
+          sup = __ballot((uint32_t)lane < wn && pnow < win.du);
+          if ((uint32_t)lane < wn) pnow = coherent_load(&vis.claim[win.ps]);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           v[u] = -1;
@@ -933,10 +964,17 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
             c[u].sbase = __builtin_amdgcn_readlane(win.sbase, k);
             c[u].lv = __builtin_amdgcn_readlane(win.lv, k);
             c[u].du = (uint32_t)__builtin_amdgcn_readlane((int32_t)win.du, k);
-            if (e0 + lane < e1) {
+            if (e0 + lane < e1 && !((sup >> k) & 1ull)) {
               v[u] = a.col[e0 + lane];
               if (P == PROB_SSSP) w[u] = a.w[e0 + lane];
             }
+          }
+        }
+        if (a.count_stats) {  // edges run (lane 0 keeps the wave's count)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const uint32_t nv = (uint32_t)__popcll(__ballot(v[u] >= 0));
+            if (lane == 0) cn.echild += nv;
           }
         }
         visit_batch<P, U>(a, vis, v, w, c, L, out);
