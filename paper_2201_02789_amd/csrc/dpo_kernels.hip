@@ -513,8 +513,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       }
       if (ser) {
         ++cn.serial;
-        if (in_regs) {  // (listed parents count their edges in pass 2)
-          cn.eser += deg;
+        if (in_regs) {
           e = start;
           end = start + deg;
           ctx = p.e;
@@ -664,6 +663,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           cs = e;
           cd = end - e;
           cc = ctx;
+          cn.eser += (uint32_t)cd;
         } else {
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(&s_ser[1], 64u);
@@ -721,7 +721,11 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       // used by the flat kernel).  A lane whose child is done takes the next
       // parent of the list, so lanes do not idle until the wave's largest
       // child finishes.
+      uint32_t pnow = 0xFFFFFFFFu;  // SSSP: the lane's parent distance when taken
       while (true) {
+        // SSSP: a parent lowered again during this level expands at the next
+        // (checked one batch after the load was issued, so nothing waits)
+        if (P == PROB_SSSP && pnow < ctx.du) end = e;
         const bool idle = e >= end;
         const unsigned long long m = __ballot(idle);
         uint32_t base = 0;
@@ -736,9 +740,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
             const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
             e = r.x;
             end = r.x + r.y;
-            // SSSP: a parent lowered again during this level expands at the next
-            if (P == PROB_SSSP && coherent_load(&vis.claim[r.z]) < (uint32_t)r.w) end = e;
-            cn.eser += (uint32_t)(end - e);
+            if (P == PROB_SSSP) pnow = coherent_load(&vis.claim[r.z]);
             ctx.vbase = Q.vbase;
             ctx.n = Q.n;
             ctx.sbase = Q.slot0 - Q.vbase;
@@ -759,7 +761,9 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         visit_batch<P, U>(a, vis, v, w, c, L, out);
 #pragma unroll
         for (int r = 0; r < U; ++r) stage_push(s, out[r] >= 0, out[r], a, cur, fout, lane);
-        e = min(e + U, end);
+        const int32_t e2 = min(e + U, end);
+        cn.eser += (uint32_t)(e2 - e);
+        e = e2;
       }
     }
   }
