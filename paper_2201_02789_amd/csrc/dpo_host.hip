@@ -28,7 +28,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t state, queries, qlist, qmap, grp_packed, grp_done, front0, front1, visit, dist2, rec, rec_q,
-      rec_slot, ser, desc, stats, total;
+      rec_slot, ser, desc, stats, sercnt, total;
   int32_t ngroups_cap, desc_cap, fcap;
 };
 
@@ -91,6 +91,7 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.ser = off; off = align_up(off + (size_t)cdiv(slots, PB) * PB * 16);
   L.desc = off; off = align_up(off + (size_t)NQD * L.desc_cap * 16);
   L.stats = off; off = align_up(off + (size_t)MAX_GRID * NSTAT * 8);
+  L.sercnt = off; off = align_up(off + (size_t)MAX_GRID * 4);
   L.total = off;
   return L;
 }
@@ -120,6 +121,7 @@ dpo_status check_graph(const dpo_csr* g, bool need_w) {
 struct CachedGraph {
   const void* parent;
   const void* child;
+  const void* serial;
   int pgrid, cgrid, steps;
   Args args;
   hipGraphExec_t exec;
@@ -201,13 +203,16 @@ dpo_status add_node(hipGraph_t graph, hipGraphNode_t* prev, const void* fn, int 
   return DPO_OK;
 }
 
-// K level steps (parent kernel, then child kernel unless flat) and the
+// K level steps (parent kernel, then child kernel unless flat, then the
+// thresholded children's kernel if any, on the parent kernel's grid) and the
 // advance of the level base, as one instantiated graph.
-dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid, int cgrid,
-                    int steps, const Args& args, hipGraphExec_t* out, bool cached = true) {
+dpo_status get_exec(Runtime& r, const void* parent, const void* child, const void* serial,
+                    int pgrid, int cgrid, int steps, const Args& args, hipGraphExec_t* out,
+                    bool cached = true) {
   for (auto& e : r.graphs) {
     if (!cached) break;
-    if (e.parent == parent && e.child == child && e.pgrid == pgrid && e.cgrid == cgrid &&
+    if (e.parent == parent && e.child == child && e.serial == serial && e.pgrid == pgrid &&
+        e.cgrid == cgrid &&
         e.steps == steps && std::memcmp(&e.args, &args, sizeof(Args)) == 0) {
       e.last_use = ++r.tick;
       *out = e.exec;
@@ -225,6 +230,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid
     void* params[] = {&a, &step_ids[i]};
     s = add_node(graph, &prev, parent, pgrid, PB, params);
     if (s == DPO_OK && child) s = add_node(graph, &prev, child, cgrid, PB, params);
+    if (s == DPO_OK && serial) s = add_node(graph, &prev, serial, pgrid, PB, params);
   }
   State* st = a.st;
   uint32_t k = (uint32_t)steps;
@@ -246,7 +252,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, int pgrid
     (void)hipGraphExecDestroy(r.graphs[victim].exec);
     r.graphs.erase(r.graphs.begin() + victim);
   }
-  r.graphs.push_back(CachedGraph{parent, child, pgrid, cgrid, steps, args, exec, ++r.tick});
+  r.graphs.push_back(CachedGraph{parent, child, serial, pgrid, cgrid, steps, args, exec, ++r.tick});
   *out = exec;
   return DPO_OK;
 }
@@ -259,6 +265,7 @@ struct SetRun {
   Args a{};
   const void* parent = nullptr;
   const void* child = nullptr;
+  const void* serial = nullptr;  // thresholded children after the child kernel
   int pgrid = 0, cgrid = 0, steps = kDefaultSteps;
   hipStream_t stream = nullptr;
   int32_t* qlist = nullptr;  // device: indices of the queries being admitted
@@ -275,6 +282,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   sr->lay = lay;
   sr->parent = parent_kernel_ptr(problem, gran);
   sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem);
+  sr->serial = serial_kernel_ptr(problem, gran);
   if (!sr->parent) return DPO_ERR_UNSUPPORTED;
   char* base = (char*)ws;
   Args& a = sr->a;
@@ -300,6 +308,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.qmap = (int32_t*)(base + lay.qmap);
   a.desc = (int4*)(base + lay.desc);
   a.stats = (unsigned long long*)(base + lay.stats);
+  a.sercnt = (uint32_t*)(base + lay.sercnt);
   a.slots = (int32_t)slots;
   a.m = g->m;
   a.nq = nq;
@@ -314,6 +323,9 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.count_stats = count_stats ? 1 : 0;
   sr->qlist = (int32_t*)(base + lay.qlist);
   sr->pgrid = persistent_grid(r, sr->parent);
+  // the thresholded children's kernel walks the lists of the parent kernel's
+  // workgroups: one grid for both, all of it resident in either
+  if (sr->serial) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->serial));
   sr->cgrid = sr->child ? persistent_grid(r, sr->child) : 0;
   sr->steps = o.steps_per_replay ? o.steps_per_replay : kDefaultSteps;
   sr->stream = (hipStream_t)stream;
@@ -399,7 +411,8 @@ dpo_status replay(Runtime& r, SetRun& sr, hipGraphExec_t exec) {
 // Runs replays until every query has finished.
 dpo_status run_to_completion(Runtime& r, SetRun& sr, int64_t max_levels) {
   hipGraphExec_t exec;
-  dpo_status s = get_exec(r, sr.parent, sr.child, sr.pgrid, sr.cgrid, sr.steps, sr.a, &exec);
+  dpo_status s =
+      get_exec(r, sr.parent, sr.child, sr.serial, sr.pgrid, sr.cgrid, sr.steps, sr.a, &exec);
   if (s != DPO_OK) return s;
   const int64_t max_replays = max_levels / sr.steps + 2;
   for (int64_t rep = 0; rep < max_replays; ++rep) {
@@ -736,8 +749,8 @@ dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_opt
     e->hq = (Query*)((char*)p + 64);
     e->hlist = (int32_t*)(e->hq + max_queries);
     std::memset(e->hq, 0, (size_t)max_queries * sizeof(Query));
-    s = get_exec(r, e->sr.parent, e->sr.child, e->sr.pgrid, e->sr.cgrid, e->sr.steps, e->sr.a,
-                 &e->exec, false);
+    s = get_exec(r, e->sr.parent, e->sr.child, e->sr.serial, e->sr.pgrid, e->sr.cgrid,
+                 e->sr.steps, e->sr.a, &e->exec, false);
   }
   if (s == DPO_OK) s = start_set(r, e->sr);
   if (s == DPO_OK &&

@@ -12,6 +12,10 @@ constexpr int NQD = 8;           // descriptor queues (one per XCD: queue = virt
 constexpr int NQF = 64;          // frontier queues (queue = workgroup % 64), plus one overflow
 constexpr int MAX_GRID = 4096;   // persistent grid cap (rows of the per-workgroup counters)
 constexpr int NSTAT = 8;
+// parent kernel phases
+constexpr int PH_BOTH = 0;    // pass 1 and pass 2
+constexpr int PH_LIST = 1;    // pass 1; thresholded parents listed for PH_SERIAL
+constexpr int PH_SERIAL = 2;  // pass 2 of the listed parents (after the child kernel)
 constexpr int MAX_QUERIES = 4096;  // per-query tables are staged in LDS
 constexpr int ADMIT_CHUNK = 4096;  // output slots initialised per admit workgroup
 constexpr int PRECHECK_MIN = 32;   // claim candidates per 512-lane batch above which
@@ -81,6 +85,7 @@ struct Args {
   int32_t* qmap;                   // [slots / 32] query owning each 32-slot chunk
   int4* desc;                      // [NQD][desc_cap] {record base, records, block base, -}
   unsigned long long* stats;       // [MAX_GRID][NSTAT], one row per workgroup
+  uint32_t* sercnt;                // [MAX_GRID] listed thresholded parents per workgroup
   int32_t slots;                   // total output slots (sum of the queries' n)
   int32_t m;                       // CSR arena entries
   int32_t nq;
@@ -102,6 +107,7 @@ struct Args {
 
 const void* parent_kernel_ptr(int problem, int gran);
 const void* child_kernel_ptr(int problem);
+const void* serial_kernel_ptr(int problem, int gran);
 const void* init_kernel_ptr(int problem);
 const void* admit_kernel_ptr(int problem);
 const void* admit_sources_kernel_ptr();

@@ -406,7 +406,12 @@ __device__ __forceinline__ Parent load_parent(const Args& a, const int32_t* fin,
 // the launching ones and writes their records (block barriers) and lists the
 // thresholded ones; pass 2 runs the listed parents' serial children with no
 // barrier, so waves do not wait on each other.
-template <int P, int G>
+//
+// PH = PH_BOTH runs both passes.  PH_LIST runs pass 1 only and leaves the
+// workgroup's list length in a.sercnt; PH_SERIAL, launched after the level's
+// child kernel on the same grid, runs pass 2 over that list (SSSP: its parents
+// are then checked against every improvement the launched children made).
+template <int P, int G, int PH>
 __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_fpre[NQF + 2];
@@ -439,7 +444,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __syncthreads();
   const uint32_t F = s_fpre[NQF + 1];
   if (F == 0) {
-    if (blockIdx.x == 0 && tid == 0) st->done = 1;
+    if (PH != PH_SERIAL && blockIdx.x == 0 && tid == 0) st->done = 1;
     return;
   }
   // visited copies of this level (every workgroup derives the same choice)
@@ -447,7 +452,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   const bool split = F >= (uint32_t)a.split_min;
   const bool stale = st->vstale[L & 1] != 0;
   const Vis vis = vis_of<P>(a, vc, split);
-  if (blockIdx.x == 0) {
+  if (PH != PH_SERIAL && blockIdx.x == 0) {
     LevelSet* z = &st->set[(L + 1) % 3];  // idle until level L + 1
     if (tid <= NQF) z->fcnt[tid] = 0;
     if (tid < NQD) z->qctr[tid] = 0;
@@ -458,7 +463,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       st->vstale[(L + 1) & 1] = (P == PROB_BFS && !split) ? 1u : 0u;
     }
   }
-  if (G == AGG_MULTI) {
+  if (G == AGG_MULTI && PH != PH_SERIAL) {
     const uint32_t nz = (L + 1) % 3;
     for (int i = blockIdx.x * PB + tid; i < a.ngroups_cap; i += gridDim.x * PB) {
       a.grp_packed[nz * a.ngroups_cap + i] = 0;
@@ -469,24 +474,25 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   Stage s{s_stage[wave], 0u};
   Counters cn{0, 0, 0, 0, 0, 0, 0};
   const uint32_t nvb = ceil_div(F, PB);
-  if (tid == 0) s_ser[0] = 0;  // thresholded parents listed by this workgroup
+  // thresholded parents listed by this workgroup
+  if (tid == 0) s_ser[0] = PH == PH_SERIAL ? a.sercnt[blockIdx.x] : 0u;
   __syncthreads();
 
   // Fold into the copy not probed at this level: one atomic per frontier
   // entry, or, for BFS after a one-copy level or with more frontier entries
   // than bitmap words, one per non-zero word of the probed bitmap.
-  const bool word_fold = P == PROB_BFS && split && (stale || F > (uint32_t)a.vwords);
+  const bool word_fold = PH != PH_SERIAL && P == PROB_BFS && split && (stale || F > (uint32_t)a.vwords);
   const bool entry_fold = P == PROB_SSSP || (split && !word_fold);
   // a workgroup with at most one virtual block keeps its thresholded parents
   // in registers (narrow levels are latency-bound)
-  const bool in_regs = nvb <= gridDim.x;
+  const bool in_regs = PH == PH_BOTH && nvb <= gridDim.x;
   int32_t e = 0, end = 0;     // this lane's serial child: edges [e, end)
   Elem ctx{0, 0, 0, 0, 0u};
 
   // ---- pass 1: every frontier entry once.  Threshold, coarsened grid size,
   // aggregation and launch records; thresholded parents go to this
   // workgroup's serial list for pass 2.
-  for (uint32_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+  for (uint32_t vb = blockIdx.x; vb < (PH == PH_SERIAL ? 0u : nvb); vb += gridDim.x) {
     const uint32_t i = vb * PB + tid;
     int32_t start = 0, deg = 0, q = 0, slot = 0;
     uint32_t du = 0, cg = 0;
@@ -643,7 +649,8 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   // ---- pass 2: the thresholded children (Sec. III-B: no launch; the parent's
   // own threads run the child work).
   __syncthreads();
-  {
+  if (PH == PH_LIST && tid == 0) a.sercnt[blockIdx.x] = s_ser[0];
+  if (PH != PH_LIST) {
     const uint32_t nser = s_ser[0];
     if (tid == 0) s_ser[1] = 0;  // next list entry
     __syncthreads();
@@ -776,8 +783,9 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   block_flush(s, a, cur, fout, tid, s_bc);
   // queries with frontier entries at this level are still running
   __syncthreads();
-  for (int i = tid; i < a.nq; i += PB)
-    if (s_live[i >> 5] & (1u << (i & 31))) a.q[i].last = (int32_t)L;
+  if (PH != PH_SERIAL)
+    for (int i = tid; i < a.nq; i += PB)
+      if (s_live[i >> 5] & (1u << (i & 31))) a.q[i].last = (int32_t)L;
   add_stats(a, s_stats, cn, tid);
 }
 
@@ -1101,20 +1109,30 @@ __global__ void advance_kernel(State* st, uint32_t steps) {
 }
 
 // ---------------------------------------------------------------- tables
-template <int P>
+template <int P, int PH>
 static const void* parent_for(int g) {
   switch (g) {
-    case AGG_NONE: return (const void*)parent_kernel<P, AGG_NONE>;
-    case AGG_WAVE: return (const void*)parent_kernel<P, AGG_WAVE>;
-    case AGG_BLOCK: return (const void*)parent_kernel<P, AGG_BLOCK>;
-    case AGG_MULTI: return (const void*)parent_kernel<P, AGG_MULTI>;
-    case AGG_FLAT: return (const void*)parent_kernel<P, AGG_FLAT>;
+    case AGG_NONE: return (const void*)parent_kernel<P, AGG_NONE, PH>;
+    case AGG_WAVE: return (const void*)parent_kernel<P, AGG_WAVE, PH>;
+    case AGG_BLOCK: return (const void*)parent_kernel<P, AGG_BLOCK, PH>;
+    case AGG_MULTI: return (const void*)parent_kernel<P, AGG_MULTI, PH>;
     default: return nullptr;
   }
 }
 
+// BFS, and the flat kernel: both passes in one kernel.  SSSP with child
+// kernels: pass 1, the child kernel, then pass 2 (serial_kernel_ptr).
 const void* parent_kernel_ptr(int problem, int gran) {
-  return problem == PROB_BFS ? parent_for<PROB_BFS>(gran) : parent_for<PROB_SSSP>(gran);
+  if (gran == AGG_FLAT)
+    return problem == PROB_BFS ? (const void*)parent_kernel<PROB_BFS, AGG_FLAT, PH_BOTH>
+                               : (const void*)parent_kernel<PROB_SSSP, AGG_FLAT, PH_BOTH>;
+  return problem == PROB_BFS ? parent_for<PROB_BFS, PH_BOTH>(gran)
+                             : parent_for<PROB_SSSP, PH_LIST>(gran);
+}
+
+const void* serial_kernel_ptr(int problem, int gran) {
+  if (problem == PROB_BFS || gran == AGG_FLAT) return nullptr;
+  return parent_for<PROB_SSSP, PH_SERIAL>(gran);
 }
 
 const void* child_kernel_ptr(int problem) {
