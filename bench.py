@@ -76,16 +76,17 @@ def agg_of(s):
     return (dpo.DPO_AGG_MULTIBLOCK, int(s.split("-")[0]))
 
 
-# Best point of the s22 BFS sweep (threshold x coarsening x granularity) on
-# MI355X; overridable from the command line.
+# Best point of each workload's sweep (threshold x coarsening x granularity,
+# and the one-copy threshold for SSSP) on MI355X; overridable from the command
+# line.
 TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4),
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
-         "sssp21": dict(threshold=128, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
+         "sssp21": dict(threshold=512, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
 
 
-SERVE_T = 64  # threshold of the serving engines (swept: 32, 64, 128)
+SERVE_T = {"bfs": 64, "sssp": 256}  # thresholds of the serving engines
 
 
 class Workload:
@@ -357,7 +358,9 @@ def summarize_profiles(args, d):
     md += [f"| {n} | {c} | {t / 1e6:.3f} | {t / c / 1e3:.2f} |" for n, (c, t) in top]
     md += ["", f"Traversals traced: {traversals}; level-step launches per traversal "
                f"{launches_per:.4g} (levels + 1).",
-           f"Level step (parent_kernel + child_kernel) kernel time per launch: **{kernel_us:.2f} us** "
+           f"Level step (parent_kernel + child_kernel"
+           f"{'; the parent kernel runs as two kernels, pass 1 before and pass 2 after the child kernel' if args.workload.startswith('sssp') else ''}"
+           f") kernel time per launch: **{kernel_us:.2f} us** "
            f"(bench line of the traced run: mean_launch_us {line['roofline']['mean_launch_us']}, "
            f"which also holds the gaps between graph nodes).", "",
            "## HBM traffic (`rocprofv3 --pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`)", "",
@@ -452,7 +455,9 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(name, opts.label()),
-                "kernel": f"level step: parent_kernel + child_kernel <{wl.kind.upper()}, {opts.label()}>",
+                "kernel": (f"level step: parent_kernel + child_kernel"
+                           f"{' + parent_kernel pass 2' if wl.kind == 'sssp' else ''} "
+                           f"<{wl.kind.upper()}, {opts.label()}>"),
                 "launches_per_traversal": float(launches.mean()),
                 "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
                 "algorithmic_bytes_per_launch": round(float(bytes_call.sum() / launches.sum()))}
@@ -679,13 +684,15 @@ def bench_serve(args, dpo, torch, full_line=False):
     da = dpo.DeviceArena(arena, vbase)
     pools = [gg.sample_sources(g, 64, 6000 + i) for i, g in enumerate(graphs)]
     log(f"[serve] graphs ready, arena n={arena.n} m={arena.m} ({time.time() - t0:.1f}s)")
-    opts = [dpo.Options(threshold=args.threshold if args.threshold is not None else SERVE_T,
-                        coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4, steps_per_replay=4)]
+    def opts(kind):
+        T = args.threshold if args.threshold is not None else SERVE_T[kind]
+        return [dpo.Options(threshold=T, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
+                            steps_per_replay=4)]
     s_bfs, s_sssp = torch.cuda.Stream(), torch.cuda.Stream()
     max_slots = 1 << 24
-    engines = {"bfs": dpo.Engine(da, "bfs", opts, max_queries=256, max_slots=max_slots,
+    engines = {"bfs": dpo.Engine(da, "bfs", opts("bfs"), max_queries=256, max_slots=max_slots,
                                  stream=s_bfs),
-               "sssp": dpo.Engine(da, "sssp", opts, max_queries=256, max_slots=max_slots,
+               "sssp": dpo.Engine(da, "sssp", opts("sssp"), max_queries=256, max_slots=max_slots,
                                   stream=s_sssp)}
     sinks = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in graphs]
     rates = [int(x) for x in args.rates.split(",")]
@@ -737,7 +744,8 @@ def bench_serve(args, dpo, torch, full_line=False):
                 "config": {"workload": "Poisson BFS/SSSP 70/30, scales 14..20 + second 20"},
                 "serving": results}
     return {"rates": results, "graphs": "R-MAT scales 14..20 + second 20, ef 16",
-            "mix": "70% BFS / 30% SSSP", "steps_per_replay": 4, "max_slots": max_slots}
+            "mix": "70% BFS / 30% SSSP", "steps_per_replay": 4, "max_slots": max_slots,
+            "thresholds": {k: opts(k)[0].threshold for k in engines}}
 
 
 # ---------------------------------------------------------------- low nesting
