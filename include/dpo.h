@@ -114,9 +114,11 @@ typedef struct {
   int64_t frontier_total;   /* parent threads run (sum of frontier sizes)          */
   int64_t serial_parents;   /* parents that ran their children serially (T)        */
   int64_t records;          /* parents that launched (launch records written)      */
-  int64_t child_blocks;     /* coarsened child blocks executed                     */
+  int64_t child_blocks;     /* coarsened child blocks started                      */
   int64_t edges_serial;     /* neighbour visits done inside parents                */
-  int64_t edges_child;      /* neighbour visits done by child blocks               */
+  int64_t edges_child;      /* neighbour visits done by child blocks; SSSP counts
+                               neither kind for a parent whose distance dropped
+                               again in its level (its work is dropped)         */
   int64_t descriptors;      /* aggregated grids published ("launches")             */
 } dpo_stats;
 
