@@ -328,6 +328,45 @@ def test_sssp_sweep_s14(s14p):
     cert.check_sssp(g, src, got)
 
 
+def _plain_frontier_bf_relaxations(g, src):
+    """Edges relaxed by a level-synchronous frontier Bellman-Ford that expands
+    every frontier vertex (each level reads the distances of the level
+    before)."""
+    rp = np.asarray(g.row_ptr, dtype=np.int64)
+    col = np.asarray(g.col_idx, dtype=np.int64)
+    w = np.asarray(g.weights, dtype=np.int64)
+    deg = np.diff(rp)
+    d = np.full(g.n, 1 << 40, dtype=np.int64)
+    d[src] = 0
+    front, total = np.array([src]), 0
+    while front.size:
+        cnt = deg[front]
+        idx = np.repeat(rp[front] - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt) + np.arange(cnt.sum())
+        v, nd = col[idx], np.repeat(d[front], cnt) + w[idx]
+        total += int(cnt.sum())
+        better = nd < d[v]
+        np.minimum.at(d, v[better], nd[better])
+        front = np.unique(v[better])
+    return total
+
+
+def test_sssp_drops_work_of_superseded_parents(s14p):
+    """A parent lowered again within its level has its work dropped: the GPU
+    relaxes fewer edges than a frontier Bellman-Ford that expands every
+    frontier vertex, and still every reached vertex's edges at least once."""
+    g, dg = s14p
+    src = gg.max_degree_vertex(g)
+    want = oracle.dijkstra(g, src)
+    plain = _plain_frontier_bf_relaxations(g, src)
+    for opts in (dpo.Options(threshold=512, coarsen=1), dpo.Options(threshold=64, coarsen=1),
+                 dpo.Options.naive()):
+        got, st = run_sssp(dg, src, opts, stats=True)
+        assert np.array_equal(got, want), opts.label()
+        done = st["edges_serial"] + st["edges_child"]
+        print("sssp work", opts.label(), done, "of", plain, flush=True)
+        assert int(g.degrees()[want != 0xFFFFFFFF].sum()) <= done < plain, opts.label()
+
+
 STRUCTURED = [
     ("path", lambda: gg.path_graph(3000), 0),
     ("cycle", lambda: gg.cycle_graph(1001), 7),
