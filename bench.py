@@ -78,12 +78,16 @@ def agg_of(s):
 
 # Best point of each workload's sweep (threshold x coarsening x granularity,
 # and the one-copy threshold for SSSP) on MI355X; overridable from the command
-# line.
-TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
-         "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4),
-         "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4),
+# line.  The original child block size (the untransformed program's child
+# blockDim, which the naive baseline shares) is 128 lanes on the large
+# workloads: the child kernel splits a level's blocks evenly over its waves,
+# and smaller blocks make equal block counts closer to equal edge counts.
+TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
+         "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4, child_block=128),
+         "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
-         "sssp21": dict(threshold=512, coarsen=1, agg=3, agg_blocks=4, split_min=262144)}
+         "sssp21": dict(threshold=512, coarsen=1, agg=3, agg_blocks=4, split_min=262144,
+                        child_block=128)}
 
 
 SERVE_T = {"bfs": 64, "sssp": 256}  # thresholds of the serving engines
@@ -464,7 +468,8 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
 
     baselines = {}
     if with_baselines:
-        for name, o in (("flat", dpo.Options.flat()), ("naive", dpo.Options.naive())):
+        for name, o in (("flat", dpo.Options.flat()),
+                        ("naive", dpo.Options.naive(child_block=opts.child_block))):
             o.steps_per_replay = opts.steps_per_replay
             pc, _ = measure(dpo, torch, wl, dg, o, 1, 1)
             g_b = edges_step / (pc.sum() * 1e-3) / 1e9

@@ -108,7 +108,8 @@ class Options:
         at = f"-A{self.agg_threshold}" if self.agg_threshold else ""
         sm = f"-S{self.split_min}" if self.split_min != 65536 else ""
         sl = "-lane" if not self.serial_wave else ""
-        return f"T{self.threshold}-CF{self.coarsen}-{g}{at}{sm}{sl}"
+        cb = f"-CB{self.child_block}" if self.child_block != 256 else ""
+        return f"T{self.threshold}-CF{self.coarsen}-{g}{cb}{at}{sm}{sl}"
 
 
 _lib = None
