@@ -589,7 +589,7 @@ def bench_batch(args, dpo, torch, full_line=False):
     log(f"[batch] {len(graphs)} graphs, {len(queries)} queries, arena n={arena.n} m={arena.m} "
         f"({time.time() - t0:.1f}s)")
     base = dpo.Options(threshold=32, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
-                       steps_per_replay=16)
+                       steps_per_replay=16, child_block=128)
     tuned, traces = autotune.tune("bfs", da, graphs, queries, bucket, 3, base, max_runs=8, log=log)
     qs = [(g, s, bucket[g]) for g, s in queries]
     tot, slot0 = dpo.dpo_batch_slots(da, qs)
@@ -622,7 +622,7 @@ def bench_batch(args, dpo, torch, full_line=False):
            "tuned": [o.label() for o in tuned],
            "tuning_runs": [len(t) for t in traces]}
     # a sample of the same queries, one dpo_bfs call each on its own graph
-    one = dpo.Options(threshold=32, coarsen=1, steps_per_replay=16)
+    one = dpo.Options(threshold=32, coarsen=1, steps_per_replay=16, child_block=128)
     sub = qs[::8]
     dgs = {g: dpo.DeviceGraph.from_host(graphs[g]) for g, _, _ in sub}
     bufs = {g: (torch.empty(graphs[g].n, dtype=torch.int32, device="cuda"),
@@ -692,7 +692,7 @@ def bench_serve(args, dpo, torch, full_line=False):
     def opts(kind):
         T = args.threshold if args.threshold is not None else SERVE_T[kind]
         return [dpo.Options(threshold=T, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
-                            steps_per_replay=4)]
+                            steps_per_replay=4, child_block=128)]
     s_bfs, s_sssp = torch.cuda.Stream(), torch.cuda.Stream()
     max_slots = 1 << 24
     engines = {"bfs": dpo.Engine(da, "bfs", opts("bfs"), max_queries=256, max_slots=max_slots,
