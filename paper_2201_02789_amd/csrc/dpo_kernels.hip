@@ -421,6 +421,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ uint32_t s_live[MAX_QUERIES / 32];  // queries seen at this level
   __shared__ uint32_t s_ser[2];                  // serial list: length, next entry
   __shared__ uint32_t s_soff[NW][64];            // per wave: scanned child sizes of a group
+  __shared__ uint32_t s_lpre[PH == PH_SERIAL ? MAX_GRID + 1 : 1];  // prefix of list lengths
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
@@ -652,7 +653,41 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   if (PH == PH_LIST && tid == 0) a.sercnt[blockIdx.x] = s_ser[0];
   if (PH != PH_LIST) {
     const uint32_t nser = s_ser[0];
-    if (tid == 0) s_ser[1] = 0;  // next list entry
+    // This workgroup's list entries [r0, r1).  PH_SERIAL: the lists are
+    // complete, and the workgroups split their concatenation evenly (a block
+    // scan of the list lengths), so each runs the same number of thresholded
+    // parents however many its own list holds.
+    uint32_t r0 = 0, r1 = nser, nl = 0;
+    if (PH == PH_SERIAL && G != AGG_FLAT && a.serial_wave) {
+      nl = min(gridDim.x, nvb);
+      constexpr int PER = MAX_GRID / PB;
+      uint32_t vals[PER], sum = 0;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t l = (uint32_t)tid * PER + j;
+        vals[j] = l < nl ? a.sercnt[l] : 0u;
+        sum += vals[j];
+      }
+      const uint32_t incl = wave_incl_scan(sum, lane);
+      if (lane == 63) s_scan[wave] = incl;
+      __syncthreads();
+      uint32_t run = incl - sum, tot = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) {
+        if (w2 < wave) run += s_scan[w2];
+        tot += s_scan[w2];
+      }
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t l = (uint32_t)tid * PER + j;
+        if (l < nl) s_lpre[l] = run;
+        run += vals[j];
+      }
+      if (tid == 0) s_lpre[nl] = tot;
+      r0 = (uint32_t)((uint64_t)blockIdx.x * tot / gridDim.x);
+      r1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * tot / gridDim.x);
+    }
+    if (tid == 0) s_ser[1] = r0;  // next list entry
     __syncthreads();
     constexpr int U = 8;
     if (G != AGG_FLAT && a.serial_wave) {
@@ -675,10 +710,21 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(&s_ser[1], 64u);
           base = __shfl(base, 0, 64);
-          if (base >= nser) break;
-          const uint32_t k = base + (uint32_t)lane;
-          if (k < nser) {
-            const int4 r = a.ser[(size_t)(blockIdx.x + (k / PB) * gridDim.x) * PB + k % PB];
+          if (base >= r1) break;
+          uint32_t k = base + (uint32_t)lane, owner = blockIdx.x;
+          if (k < r1) {
+            if (PH == PH_SERIAL) {
+              // list holding entry k of the concatenation: the last list
+              // whose prefix is <= k (empty lists share their successor's)
+              uint32_t lo = 0, hi = nl;
+              while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_lpre[mid] <= k) lo = mid; else hi = mid;
+              }
+              owner = lo;
+              k -= s_lpre[lo];
+            }
+            const int4 r = a.ser[(size_t)(owner + (k / PB) * gridDim.x) * PB + k % PB];
             const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
             cs = r.x;
             cd = r.y;
