@@ -16,6 +16,7 @@ constexpr int NSTAT = 8;
 constexpr int PH_BOTH = 0;    // pass 1 and pass 2
 constexpr int PH_LIST = 1;    // pass 1; thresholded parents listed for PH_SERIAL
 constexpr int PH_SERIAL = 2;  // pass 2 of the listed parents (after the child kernel)
+constexpr uint32_t GROUP_EDGES = 1024;  // wave-run serial children: edges per group (about)
 constexpr int MAX_QUERIES = 4096;  // per-query tables are staged in LDS
 constexpr int ADMIT_CHUNK = 4096;  // output slots initialised per admit workgroup
 constexpr int PRECHECK_MIN = 32;   // claim candidates per 512-lane batch above which

@@ -707,24 +707,47 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           cc = ctx;
           cn.eser += (uint32_t)cd;
         } else {
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(&s_ser[1], 64u);
-          base = __shfl(base, 0, 64);
-          if (base >= r1) break;
-          uint32_t k = base + (uint32_t)lane, owner = blockIdx.x;
-          if (k < r1) {
-            if (PH == PH_SERIAL) {
-              // list holding entry k of the concatenation: the last list
-              // whose prefix is <= k (empty lists share their successor's)
-              uint32_t lo = 0, hi = nl;
-              while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_lpre[mid] <= k) lo = mid; else hi = mid;
+          uint32_t base = 0, n = 64;
+          int4 r = make_int4(0, 0, 0, 0);
+          if (PH == PH_SERIAL) {
+            // Claim the next entries of this workgroup's range whose children
+            // total at most GROUP_EDGES edges (at least one entry): groups of
+            // similar length, so no wave's last group holds up its workgroup.
+            while (true) {
+              if (lane == 0)
+                base = __hip_atomic_load(&s_ser[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              base = __shfl(base, 0, 64);
+              if (base >= r1) break;
+              uint32_t k = base + (uint32_t)lane;
+              uint32_t dg = 0;
+              if (k < r1) {
+                // list holding entry k of the concatenation: the last list
+                // whose prefix is <= k (empty lists share their successor's)
+                uint32_t lo = 0, hi = nl;
+                while (hi - lo > 1) {
+                  const uint32_t mid = (lo + hi) >> 1;
+                  if (s_lpre[mid] <= k) lo = mid; else hi = mid;
+                }
+                k -= s_lpre[lo];
+                r = a.ser[(size_t)(lo + (k / PB) * gridDim.x) * PB + k % PB];
+                dg = (uint32_t)r.y;
               }
-              owner = lo;
-              k -= s_lpre[lo];
+              const uint32_t inc = wave_incl_scan(dg, lane);
+              n = (uint32_t)__popcll(__ballot(base + (uint32_t)lane < r1 && inc <= GROUP_EDGES));
+              n = max(n, 1u);
+              uint32_t won = 0;
+              if (lane == 0) won = atomicCAS(&s_ser[1], base, base + n) == base ? 1u : 0u;
+              if (__shfl(won, 0, 64)) break;
             }
-            const int4 r = a.ser[(size_t)(owner + (k / PB) * gridDim.x) * PB + k % PB];
+          } else {
+            if (lane == 0) base = atomicAdd(&s_ser[1], 64u);
+            base = __shfl(base, 0, 64);
+            const uint32_t k = base + (uint32_t)lane;
+            if (k < r1) r = a.ser[(size_t)(blockIdx.x + (k / PB) * gridDim.x) * PB + k % PB];
+            n = base < r1 ? min(64u, r1 - base) : 0u;
+          }
+          if (base >= r1) break;
+          if ((uint32_t)lane < n) {
             const Query Q = a.q[a.qmap[(uint32_t)r.z >> 5]];
             cs = r.x;
             cd = r.y;
