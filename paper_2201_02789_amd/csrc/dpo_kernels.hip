@@ -508,7 +508,11 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
       atomicOr(&s_live[p.q >> 5], 1u << (p.q & 31));
       if (P == PROB_SSSP) {
         du = vis.probe[slot];
-        atomicMin(&vis.fold[slot], du);
+        // PH_LIST runs before any relaxation of its level, so this is the
+        // entry's only writer and du is never above the value it replaces
+        // (the copy lacks just the frontier's improvements): a plain store
+        if (PH == PH_LIST) vis.fold[slot] = du;
+        else atomicMin(&vis.fold[slot], du);
       } else if (entry_fold) {
         atomicOr(&vis.fold[(uint32_t)slot >> 5], 1u << (slot & 31));
       }
