@@ -1,6 +1,8 @@
 // Device code: level-synchronous nested-parallel BFS / SSSP for gfx950.
 //
-// Each level is two kernels.
+// Each level is two kernels, the parent kernel and the child kernel; for SSSP
+// the parent kernel's second pass (the thresholded children) runs as a third
+// kernel after the child kernel.
 //
 // Parent kernel: the parent grid.  Workgroups (256 lanes = 4 wave64) take
 // virtual parent blocks of 256 frontier entries in a grid-stride loop; lane i
