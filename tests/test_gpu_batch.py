@@ -55,7 +55,9 @@ def run_batch(kind, da, qs, bopts, stats=False):
 MODES = [dict(), dict(agg=dpo.DPO_AGG_WAVE), dict(agg=dpo.DPO_AGG_BLOCK),
          dict(agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=16), dict(agg=dpo.DPO_AGG_NONE),
          dict(mode=dpo.DPO_MODE_FLAT), dict(child_block=64, steps_per_replay=2),
-         dict(split_min=0), dict(split_min=256, steps_per_replay=3), dict(serial_wave=0)]
+         dict(split_min=0), dict(split_min=256, steps_per_replay=3), dict(serial_wave=0),
+         dict(child_block=128), dict(agg=dpo.DPO_AGG_GRID, child_block=128),
+         dict(agg=dpo.DPO_AGG_NONE, child_block=128, split_min=0)]
 
 
 @pytest.mark.parametrize("common", MODES, ids=[str(m) for m in MODES])
@@ -78,7 +80,7 @@ def test_bfs_batch_matches_oracle_per_query(mixed, common):
     assert got_counts == want_counts, common
 
 
-SSSP_MODES = MODES[:4] + MODES[5:6] + MODES[7:]
+SSSP_MODES = MODES
 
 
 @pytest.mark.parametrize("common", SSSP_MODES, ids=[str(m) for m in SSSP_MODES])
@@ -110,20 +112,72 @@ def test_repeated_queries_identical(mixed):
         assert np.array_equal(host[slot0[i]:slot0[i] + graphs[g].n], first)
 
 
-@pytest.mark.slow
-def test_batch_512_queries_over_64_graphs_bfs():
-    """The batched workload: 512 BFS over 64 R-MAT graphs, scales 10..18."""
+@pytest.fixture(scope="module")
+def batch512():
     graphs, queries = gg.batch_workload()
     arena, vbase = gg.pack_arena(graphs)
+    wants = [oracle.bfs(graphs[g], s)[0] for g, s in queries]
+    return graphs, queries, dpo.DeviceArena(arena, vbase), wants
+
+
+def bench_bucket_options():
+    """The batched benchmark's bucket split (scales 10-12, 13-15, 16-18) and
+    per-bucket options at the points its tuner has chosen on MI355X, and its
+    untuned base point."""
+    base = dict(threshold=32, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
+                child_block=128)
+    tuned = [dpo.Options(**base), dpo.Options(**base), dpo.Options(**{**base, "threshold": 128})]
+    return tuned, [dpo.Options(**base)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("which", ["tuned", "untuned", "two-buckets-CB256", "16-block",
+                                   "grid", "lane-serial"])
+def test_batch_512_queries_over_64_graphs_bfs(batch512, which):
+    """The batched workload: 512 BFS over 64 R-MAT graphs, scales 10..18, at
+    the benchmarked per-bucket options and other granularities; every query
+    against the oracle, and the counters against the summed schedule counts."""
+    graphs, queries, da, wants = batch512
+    scales = [int(np.log2(g.n)) for g in graphs]
+    bucket3 = [0 if sc <= 12 else (1 if sc <= 15 else 2) for sc in scales]
+    tuned, untuned = bench_bucket_options()
+    if which == "two-buckets-CB256":
+        bopts = bucket_opts()
+        bucket = [0 if g.n < 2**14 else 1 for g in graphs]
+    else:
+        bopts = {"tuned": tuned, "untuned": untuned,
+                 "16-block": [dpo.Options(**{**o.__dict__, "agg_blocks": 16}) for o in tuned],
+                 "grid": [dpo.Options(**{**o.__dict__, "agg": dpo.DPO_AGG_GRID}) for o in tuned],
+                 "lane-serial": [dpo.Options(**{**o.__dict__, "serial_wave": 0}) for o in tuned],
+                 }[which]
+        bucket = bucket3 if len(bopts) == 3 else [0] * len(graphs)
+    qs = [(g, s, bucket[g]) for g, s in queries]
+    print("batch512", which, [o.label() for o in bopts], flush=True)
+    host, slot0, st = run_batch("bfs", da, qs, bopts, stats=True)
+    want_counts = {}
+    for i, (g, s, b) in enumerate(qs):
+        assert np.array_equal(host[slot0[i]:slot0[i] + graphs[g].n], wants[i]), (which, i)
+        c = oracle.schedule_counts(graphs[g], wants[i], bopts[b].threshold, bopts[0].child_block,
+                                   bopts[b].coarsen)
+        for k, v in c.items():
+            want_counts[k] = want_counts.get(k, 0) + v
+    assert {k: st[k] for k in want_counts} == want_counts, which
+
+
+@pytest.mark.slow
+def test_batch_512_queries_sssp_tuned_options(batch512):
+    """SSSP over the batched workload's graphs (weighted) at the tuned bucket
+    options: every query against the oracle."""
+    graphs, queries, _, _ = batch512
+    wg = [gg.add_weights(g, 700 + i) for i, g in enumerate(graphs)]
+    arena, vbase = gg.pack_arena(wg)
     da = dpo.DeviceArena(arena, vbase)
-    qs = [(g, s, 0 if graphs[g].n < 2**14 else 1) for g, s in queries]
-    host, slot0, _ = run_batch("bfs", da, qs, bucket_opts())
+    scales = [int(np.log2(g.n)) for g in wg]
+    bucket = [0 if sc <= 12 else (1 if sc <= 15 else 2) for sc in scales]
+    tuned, _ = bench_bucket_options()
+    qs = [(g, s, bucket[g]) for g, s in queries[::2]]
+    host, slot0, _ = run_batch("sssp", da, qs, tuned)
+    host = host.view(np.uint32)
     for i, (g, s, _) in enumerate(qs):
-        if i % 7:
-            continue  # every 7th query against the oracle; all against certificates below
-        want, _ = oracle.bfs(graphs[g], s)
-        assert np.array_equal(host[slot0[i]:slot0[i] + graphs[g].n], want), i
-    from tests import certificates as cert
-    for i, (g, s, _) in enumerate(qs[::5]):
-        j = i * 5
-        cert.check_bfs(graphs[g], s, host[slot0[j]:slot0[j] + graphs[g].n])
+        want = oracle.dijkstra(wg[g], s)
+        assert np.array_equal(host[slot0[i]:slot0[i] + wg[g].n], want), i

@@ -93,8 +93,21 @@ def test_engine_rejects_oversized_and_bad_queries(resident):
     eng.close()
 
 
+def _serving_opts(which):
+    if which == "bench":
+        # the serving benchmark's engines: 128-lane child blocks, a threshold
+        # per kind
+        import bench
+        return {k: [dpo.Options(threshold=bench.SERVE_T[k], coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK,
+                                agg_blocks=4, steps_per_replay=4, child_block=128)]
+                for k in ("bfs", "sssp")}
+    o = [dpo.Options(threshold=32, coarsen=1, steps_per_replay=4)]
+    return {"bfs": o, "sssp": o}
+
+
 @pytest.mark.slow
-def test_engines_at_the_serving_shape():
+@pytest.mark.parametrize("which", ["T32-CB256", "bench"])
+def test_engines_at_the_serving_shape(which):
     """The serving workload's shape: 8 resident weighted R-MAT graphs (scales
     14..20 and a second 20), a BFS engine and an SSSP engine on two streams
     stepping together, queries arriving in waves while others run.  Every
@@ -103,9 +116,10 @@ def test_engines_at_the_serving_shape():
               for i, sc in enumerate([14, 15, 16, 17, 18, 19, 20, 20])]
     arena, vbase = gg.pack_arena(graphs)
     da = dpo.DeviceArena(arena, vbase)
-    opts = [dpo.Options(threshold=32, coarsen=1, steps_per_replay=4)]
+    kopts = _serving_opts(which)
     streams = {k: torch.cuda.Stream() for k in ("bfs", "sssp")}
-    engines = {k: dpo.Engine(da, k, opts, max_queries=64, max_slots=1 << 23, stream=streams[k])
+    engines = {k: dpo.Engine(da, k, kopts[k], max_queries=64, max_slots=1 << 23,
+                             stream=streams[k])
                for k in ("bfs", "sssp")}
     rng = np.random.default_rng(21)
     reqs = []
@@ -137,7 +151,7 @@ def test_engines_at_the_serving_shape():
     dgs = {}
     for i, (key, (kind, g, s, o)) in enumerate(outs.items()):
         dg = dgs.setdefault(g, dpo.DeviceGraph.from_host(graphs[g]))
-        lone, _ = (dpo.bfs if kind == "bfs" else dpo.sssp)(dg, s, opts[0])
+        lone, _ = (dpo.bfs if kind == "bfs" else dpo.sssp)(dg, s, kopts[kind][0])
         assert np.array_equal(lone.cpu().numpy(), o.cpu().numpy()), (kind, g, s)
         if i % 9 == 0:
             want = oracle.bfs(graphs[g], s)[0] if kind == "bfs" else oracle.dijkstra(graphs[g], s)
