@@ -37,19 +37,27 @@ def parse():
     p.add_argument("--workload", default="bfs22",
                    choices=["bfs22", "bfs25", "er22", "sssp21", "bfs12", "batch", "serve", "road"])
     p.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
-    p.add_argument("--serve-seconds", type=float, default=0.5)
+    p.add_argument("--serve-seconds", type=float, default=10.0,
+                   help="arrivals per offered rate (capped at 25,000 queries)")
+    p.add_argument("--cpu-serve-queries", type=int, default=600,
+                   help="arrivals of the lowest-rate trace that the oracle pool serves")
     p.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
     p.add_argument("--threshold", type=int, default=None)
     p.add_argument("--coarsen", type=int, default=None)
     p.add_argument("--split-min", type=int, default=None,
                    help="frontier size from which a level uses two visited copies")
     p.add_argument("--agg", default=None, help="none|wave|block|<k>-block")
+    p.add_argument("--breakdown", action="store_true",
+                   help="execution-time breakdown (Sec. VIII-B) of bfs22 or sssp21 at CF 1..8")
     p.add_argument("--sweep", action="store_true",
                    help="threshold x coarsening x granularity sweep of the workload instead")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-baselines", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="minimum oracle time of the cpu_baseline sample")
+    p.add_argument("--calibrate-primitives", action="store_true",
+                   help="only run the memory-primitive microbenchmarks and write "
+                        "profiles/primitives.md")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 512 MiB device copy (counter calibration)")
     p.add_argument("--summarize-profiles", metavar="DIR", default=None,
@@ -164,54 +172,63 @@ def measure(dpo, torch, wl, dg, opts, steps, warmup, sources=None):
     return per_call, wall
 
 
-def certify(g, kind, src, out):
-    """Edge certificates of one result (no oracle): BFS (i) level[s] = 0,
-    (ii) every reached v != s has an in-neighbour one level lower, (iii) every
-    edge from a reached u reaches v with level[v] <= level[u] + 1; SSSP the same
-    with dist and w (>= 1).  Together they fix levels / distances exactly."""
-    rp = np.asarray(g.row_ptr, dtype=np.int64)
-    u = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(rp))
-    v = np.asarray(g.col_idx, dtype=np.int32)
-    if kind == "bfs":
-        x = out.astype(np.int64)
-        unreached, step = -1, 1
-    else:
-        x = out.astype(np.int64) & 0xFFFFFFFF
-        unreached, step = 0xFFFFFFFF, np.asarray(g.weights, dtype=np.int64)
-    if x[src] != 0:
-        return False
-    xu, xv = x[u], x[v]
-    ru = xu != unreached
-    bound = xu + step
-    if np.any(ru & ((xv == unreached) | (xv > bound))):
-        return False
-    tight = np.zeros(g.n, dtype=bool)
-    tight[v[ru & (xv == bound)]] = True
-    need = x != unreached
-    need[src] = False
-    return bool(np.all(tight[need]))
+class Certifier:
+    """Edge certificates of a traversal result, computed with torch's own
+    gather / scatter kernels on the device (independent of the HIP path, no
+    oracle): BFS (i) level[s] = 0, (ii) every reached v != s has an
+    in-neighbour one level lower, (iii) every edge from a reached u reaches v
+    with level[v] <= level[u] + 1; SSSP the same with dist and w (>= 1).
+    Together they fix levels / distances exactly."""
+
+    def __init__(self, torch, dg):
+        self.torch = torch
+        deg = (dg.row_ptr[1:] - dg.row_ptr[:-1]).to(torch.int64)
+        self.u = torch.repeat_interleave(torch.arange(dg.n, device=deg.device), deg)
+        self.v = dg.col_idx.to(torch.int64)
+        self.w = None if dg.weights is None else dg.weights.to(torch.int64) & 0xFFFFFFFF
+        self.n = dg.n
+
+    def __call__(self, kind, src, out):
+        torch = self.torch
+        if kind == "bfs":
+            x = out.to(torch.int64)
+            unreached, step = -1, 1
+        else:
+            x = out.to(torch.int64) & 0xFFFFFFFF
+            unreached, step = 0xFFFFFFFF, self.w
+        if int(x[src]) != 0:
+            return False
+        xu, xv = x[self.u], x[self.v]
+        ru = xu != unreached
+        bound = xu + step
+        if bool(torch.any(ru & ((xv == unreached) | (xv > bound)))):
+            return False
+        tight = torch.zeros(self.n, dtype=torch.bool, device=x.device)
+        tight[self.v[ru & (xv == bound)]] = True
+        need = x != unreached
+        need[src] = False
+        return bool(torch.all(tight[need]))
 
 
 def reached_stats(dpo, torch, wl, dg, opts):
     """(m_r, n_r, stats) per source from one untimed run with counters, and
-    whether the first source's result passes its edge certificates."""
+    how many sources' results pass their edge certificates."""
     out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
     ws = dpo.alloc_workspace(dg, opts)
-    deg = np.diff(wl.g.row_ptr).astype(np.int64)
-    res, ok = [], None
+    deg = torch.diff(dg.row_ptr).to(torch.int64)
+    cert = Certifier(torch, dg)
+    res, passed = [], 0
     for s in wl.sources:
         if wl.kind == "bfs":
             st = dpo.dpo_bfs(dg, int(s), opts, out, ws, stats=True)
-            host = out.cpu().numpy()
-            reached = host >= 0
+            reached = out >= 0
         else:
             st = dpo.dpo_sssp(dg, int(s), opts, out, ws, stats=True)
-            host = out.cpu().numpy()
-            reached = dpo.as_uint32(out) != 0xFFFFFFFF
-        if ok is None:
-            ok = certify(wl.g, wl.kind, int(s), host)
+            reached = out != -1  # 0xFFFFFFFF as int32
+        passed += int(cert(wl.kind, int(s), out))
         res.append((int(deg[reached].sum()), int(reached.sum()), st))
-    return res, ok
+    del cert
+    return res, passed
 
 
 KERNEL_SOURCES = ["paper_2201_02789_amd/csrc/dpo_kernels.hip",
@@ -228,11 +245,11 @@ def kernel_sources_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload, options_label):
-    """HBM bytes per launch from the committed counter summary
-    (profiles/<workload>_traffic.json: FETCH_SIZE and WRITE_SIZE per traversal,
-    scaled by a plain copy of known size), or None when the kernels changed
-    since the counters were taken or the options differ."""
+def measured_traffic(workload, options_label, key="hbm_bytes_per_launch"):
+    """HBM bytes per launch (or another field) from the committed counter
+    summary (profiles/<workload>_traffic.json: FETCH_SIZE and WRITE_SIZE per
+    traversal, scaled by a plain copy of known size), or None when the kernels
+    changed since the counters were taken or the options differ."""
     path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -240,7 +257,7 @@ def measured_traffic(workload, options_label):
         t = json.load(f)
     if t.get("kernel_sources_sha256") != kernel_sources_sha() or t.get("options") != options_label:
         return None
-    return t["hbm_bytes_per_launch"]
+    return t.get(key)
 
 
 def algorithmic_bytes(kind, m_r, n_r):
@@ -287,6 +304,88 @@ def cpu_baseline(wl, min_seconds=10.0, max_seconds=30.0):
             "sample": f"{runs} traversals over the workload's {len(wl.sources)} source(s) in order, "
                       f"one full {'queue BFS' if wl.kind == 'bfs' else 'binary-heap Dijkstra'} each, "
                       f"single thread, {dt:.1f} s"}
+
+
+# ---------------------------------------------------------------- calibration
+_calib = None
+
+
+def calib_lib():
+    """libdpo_calib.so: the primitive microbenchmarks (measurement only)."""
+    global _calib
+    if _calib is None:
+        import ctypes
+        path = os.path.join(ROOT, "paper_2201_02789_amd", "libdpo_calib.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        vp, u32, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
+        L.dpo_calib_random_loads.argtypes = [vp, u32, u32, i32, vp, vp]
+        L.dpo_calib_stream.argtypes = [vp, u32, i32, i32, vp, vp]
+        L.dpo_calib_stream_probe.argtypes = [vp, u32, vp, u32, i32, vp, vp]
+        L.dpo_calib_random_atomic_or.argtypes = [vp, u32, u32, i32, vp]
+        L.dpo_calib_workgroup_atomics.argtypes = [vp, u32, u32, i32, vp]
+        _calib = L
+    return _calib
+
+
+def _timed(torch, fn, reps=3):
+    """Best of reps: ms of fn(stream_ptr) between two events on torch's stream."""
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps + 1):  # the first run warms up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if fn(stream.cuda_stream) != 0:
+            raise RuntimeError("calibration launch failed")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def random_load_rate(torch, table_bytes, grid=2048, iters=32):
+    """Random 4-byte loads per second from a table of table_bytes (a power of
+    two), 8 independent loads in flight per lane."""
+    L = calib_lib()
+    words = table_bytes // 4
+    table = torch.ones(words, dtype=torch.int32, device="cuda")
+    out = torch.empty(grid * 256, dtype=torch.int32, device="cuda")
+    ms = _timed(torch, lambda st: L.dpo_calib_random_loads(table.data_ptr(), words, iters, grid,
+                                                           out.data_ptr(), st))
+    return grid * 256 * iters * 8 / (ms * 1e-3)
+
+
+def calibrate_primitives(torch):
+    """Rates of the memory primitives the level kernels are built from."""
+    L = calib_lib()
+    grid = 2048
+    out = torch.empty(grid * 256, dtype=torch.int32, device="cuda")
+    res = {}
+    for kb in (512, 8 << 10, 16 << 10, 256 << 10):
+        res[f"random_load_{kb}KiB_G_per_s"] = round(random_load_rate(torch, kb << 10) / 1e9, 1)
+    n = 128 << 20  # 512 MiB of int32
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    ms = _timed(torch, lambda st: L.dpo_calib_stream(a.data_ptr(), n, 0, grid, out.data_ptr(), st))
+    res["stream_int32_GB_per_s"] = round(n * 4 / (ms * 1e-3) / 1e9, 1)
+    ms = _timed(torch, lambda st: L.dpo_calib_stream(a.data_ptr(), n // 4, 1, grid, out.data_ptr(), st))
+    res["stream_int4_GB_per_s"] = round(n * 4 / (ms * 1e-3) / 1e9, 1)
+    col = torch.randint(0, 1 << 22, (n,), dtype=torch.int32, device="cuda")
+    table = torch.ones(1 << 17, dtype=torch.int32, device="cuda")  # 512 KiB
+    ms = _timed(torch, lambda st: L.dpo_calib_stream_probe(col.data_ptr(), n, table.data_ptr(), 1 << 17,
+                                                           grid, out.data_ptr(), st))
+    res["stream_probe_512KiB_G_elems_per_s"] = round(n / (ms * 1e-3) / 1e9, 1)
+    del col, a
+    for kb in (512, 64 << 10):
+        words = (kb << 10) // 4
+        t = torch.zeros(words, dtype=torch.int32, device="cuda")
+        ms = _timed(torch, lambda st: L.dpo_calib_random_atomic_or(t.data_ptr(), words, 8, grid, st))
+        res[f"random_atomic_or_{kb}KiB_G_per_s"] = round(grid * 256 * 8 * 8 / (ms * 1e-3) / 1e9, 2)
+    ctr = torch.zeros(8 * 32, dtype=torch.int32, device="cuda")
+    for naddr in (1, 8):
+        ms = _timed(torch, lambda st: L.dpo_calib_workgroup_atomics(ctr.data_ptr(), naddr, 16, grid, st))
+        res[f"workgroup_atomic_{naddr}_address_ns_per_op"] = round(ms * 1e6 / (grid * 16), 3)
+    return res
 
 
 # ---------------------------------------------------------------- profiles
@@ -374,6 +473,16 @@ def summarize_profiles(args, d):
            f"write {write_b / 1e6:.2f} MB, total **{(fetch_b + write_b) / 1e6:.2f} MB** "
            f"vs algorithmic {alg / 1e6:.2f} MB ({(fetch_b + write_b) / alg:.2f}x).", "",
            f"kernel_sources_sha256 `{traffic['kernel_sources_sha256']}`", ""]
+    # the same counters per level kernel (FETCH / WRITE per traversal)
+    md += ["### Per kernel (per traversal)", "", "| kernel | fetch MB | write MB |", "|---|---|---|"]
+    per_k = {}
+    for n, v in fetch:
+        per_k.setdefault(n, [0.0, 0.0])[0] += v * 1024 * sf / trav_pmc
+    for n, v in write:
+        per_k.setdefault(n, [0.0, 0.0])[1] += v * 1024 * sw / trav_pmc
+    md += [f"| {n} | {f / 1e6:.1f} | {w / 1e6:.1f} |" for n, (f, w) in sorted(per_k.items())]
+    md += [""]
+    traffic["per_kernel_bytes_per_traversal"] = {n: [round(f), round(w)] for n, (f, w) in per_k.items()}
     l2 = os.path.join(d, "l2")
     if os.path.isdir(l2):
         # L2 requests of the child kernel (counter run of its own; TCC_* summed
@@ -399,6 +508,23 @@ def summarize_profiles(args, d):
                f"for random 4-byte loads from a 512 KB table (one request per L2 channel "
                f"and clock).", ""]
         traffic["l2_requests_per_s"] = round(req / ns * 1e9)
+        # every level kernel: L2 requests, hit rate and request rate over all its dispatches
+        allk = {}
+        for r in rows:
+            n = _short(r["Kernel_Name"])
+            if not n.startswith(step):
+                continue
+            e = allk.setdefault(n, {}).setdefault(
+                r["Dispatch_Id"], {"ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+        md += ["| kernel | dispatches | L2 requests (M) | hit rate | G requests/s |", "|---|---|---|---|---|"]
+        for n, dd in sorted(allk.items()):
+            q = sum(e.get("TCC_REQ_sum", 0) for e in dd.values())
+            h = sum(e.get("TCC_HIT_sum", 0) for e in dd.values())
+            mi = sum(e.get("TCC_MISS_sum", 0) for e in dd.values())
+            t = sum(e["ns"] for e in dd.values())
+            md.append(f"| {n} | {len(dd)} | {q / 1e6:.1f} | {h / max(h + mi, 1):.3f} | {q / max(t, 1):.1f} |")
+        md.append("")
     out_json = os.path.join(ROOT, "profiles", f"{args.workload}_traffic.json")
     with open(out_json, "w") as f:
         json.dump(traffic, f, indent=1)
@@ -428,13 +554,14 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
     opts = dpo.Options(**tuned)
 
     if args.sweep:
-        sweep(dpo, torch, wl, dg)
+        sweep(dpo, torch, wl, dg, "python3 bench.py " + " ".join(sys.argv[1:]))
         return None
 
     # untimed run with counters: edges reached and level count per source
     rs, certified = reached_stats(dpo, torch, wl, dg, opts)
-    if not certified:
-        log(f"[bench] ERROR: the result of source {int(wl.sources[0])} fails its edge certificates")
+    if certified != len(wl.sources):
+        log(f"[bench] ERROR: {len(wl.sources) - certified} of {len(wl.sources)} results fail "
+            f"their edge certificates")
     levels = max(r[2]["levels"] for r in rs)
     opts.steps_per_replay = levels + 1  # one replay covers a traversal
     m_r = np.array([r[0] for r in rs], dtype=np.float64)
@@ -466,6 +593,25 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
                 "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
                 "algorithmic_bytes_per_launch": round(float(bytes_call.sum() / launches.sum()))}
 
+    # second roofline: the child body's dependent random probes (BFS: the
+    # n-bit visited bitmap; SSSP: the n-word distance array), one per edge
+    # run, against the rate the chip sustains for random 4-byte loads from a
+    # table of that size (measured here, 8 loads in flight per lane)
+    probed_bytes = wl.g.n // 8 if wl.kind == "bfs" else 4 * wl.g.n
+    table = 1 << max(12, int(np.ceil(np.log2(max(probed_bytes, 1)))))
+    ceiling = random_load_rate(torch, table)
+    probes = np.array([r[2]["edges_serial"] + r[2]["edges_child"] for r in rs], dtype=np.float64)
+    p_rate = float((probes.sum() / launches.sum()) / ((mean_call_ms.sum() * 1e-3) / launches.sum()))
+    counters = measured_traffic(name, opts.label(), "l2_requests_per_s")
+    roofline_probe = {"bound": "random 4-byte loads", "achieved": round(p_rate / 1e9, 2),
+                      "peak": round(ceiling / 1e9, 2), "unit": "G loads/s",
+                      "frac": round(p_rate / ceiling, 4),
+                      "table_bytes": table, "probes_per_traversal": float(probes.mean()),
+                      "child_l2_requests_per_s_counters": counters,
+                      "hbm_frac_cap": round(float(bytes_call.sum() / probes.sum()) * ceiling / 1e9
+                                            / HBM_PEAK_GBS, 4)}
+    log(f"[bench] probes {p_rate / 1e9:.1f} G/s of {ceiling / 1e9:.1f} G/s measured ceiling")
+
     baselines = {}
     if with_baselines:
         for name, o in (("flat", dpo.Options.flat()),
@@ -476,6 +622,20 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
             baselines[name] = {"gteps": round(g_b, 3), "ms_per_step": round(float(pc.sum()), 3),
                                "options": o.label()}
             log(f"[bench] {name}: {g_b:.3f} GTEPS")
+
+    # the same options with the paper's literal serial children (each in its
+    # parent's lane, Sec. III-B) and with the library's default replay length
+    # (16 level steps per replay instead of the traversal's level count + 1)
+    variants = {}
+    if with_baselines:
+        for vname, over in (("serial_wave_0", {"serial_wave": 0}),
+                            ("default_steps_per_replay", {"steps_per_replay": 0})):
+            o = dpo.Options(**{**opts.__dict__, **over})
+            pc, _ = measure(dpo, torch, wl, dg, o, max(1, min(steps, 3)), 1)
+            g_v = edges_step * pc.shape[0] / (pc.sum() * 1e-3) / 1e9
+            variants[vname] = {"gteps": round(g_v, 3), "ms_per_step": round(float(pc.sum(axis=1).mean()), 3),
+                               "options": o.label(), "steps_per_replay": o.steps_per_replay or 16}
+            log(f"[bench] {vname}: {g_v:.3f} GTEPS")
 
     cpu = None
     if with_cpu:
@@ -505,14 +665,16 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
                    "directed_edges_per_s": round(2 * gteps * 1e9),
                    "ms_per_traversal_mean": round(float(per_call.mean()), 4),
                    "ms_per_traversal_median": round(float(np.median(per_call)), 4),
-                   "verified": (f"edge certificates of source {int(wl.sources[0])}'s result "
-                                f"({'pass' if certified else 'FAIL'}), untimed run"),
+                   "verified": (f"edge certificates {certified}/{len(wl.sources)} pass "
+                                f"(every source's result, untimed run with the timed options)"),
                    # edges the traversal actually relaxes per reached directed edge
                    # (1 for BFS; above 1 for the frontier Bellman-Ford of SSSP)
                    "work_efficiency": round(float(np.mean(
                        [(r[2]["edges_serial"] + r[2]["edges_child"]) / max(r[0], 1) for r in rs])), 3)},
         "roofline": roofline,
+        "roofline_probe": roofline_probe,
         "baselines": baselines,
+        "variants": variants,
         "speedup_vs_flat": round(gteps / baselines["flat"]["gteps"], 2) if baselines else None,
         "speedup_vs_naive": round(gteps / baselines["naive"]["gteps"], 2) if baselines else None,
         "cpu_baseline": cpu,
@@ -544,7 +706,22 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": COPY_REPS}))
         return
     dpo.lib()  # fail loudly if the HIP library is missing
+    if args.calibrate_primitives:
+        res = calibrate_primitives(torch)
+        cmd = "python3 bench.py " + " ".join(sys.argv[1:])
+        md = ["# Memory primitives of the level kernels (MI355X)", "",
+              f"Command (repository root): `{cmd}` (kernels in "
+              "`paper_2201_02789_amd/csrc/dpo_calib.hip`; best of 3 after a warm-up, HIP events; "
+              "2048 workgroups of 256 lanes)", "", "| primitive | rate |", "|---|---|"]
+        md += [f"| {k} | {v} |" for k, v in res.items()]
+        with open(os.path.join(ROOT, "profiles", "primitives.md"), "w") as f:
+            f.write("\n".join(md) + "\n")
+        print(json.dumps(res), flush=True)
+        return
 
+    if args.breakdown:
+        print(json.dumps(bench_breakdown(args, dpo, torch)), flush=True)
+        return
     if args.workload == "batch":
         print(json.dumps(bench_batch(args, dpo, torch, full_line=True)), flush=True)
         return
@@ -562,11 +739,13 @@ def main():
     if not args.no_extras and args.workload == "bfs22":
         torch.cuda.empty_cache()
         # the SSSP half of the metric: s21, tuned options, flat and naive beside it
-        sp = workload_line(args, dpo, torch, "sssp21", 3, 1, False, True, overrides=False)
+        sp = workload_line(args, dpo, torch, "sssp21", 3, 1, not args.no_cpu, True,
+                           overrides=False)
         del sp["_graph"]
         line["sssp"] = {k: sp[k] for k in ("value", "unit", "ms_per_step", "dtype", "config",
-                                             "roofline", "baselines", "speedup_vs_flat",
-                                             "speedup_vs_naive")}
+                                             "roofline", "roofline_probe", "baselines", "variants",
+                                             "speedup_vs_flat", "speedup_vs_naive",
+                                             "cpu_baseline")}
         torch.cuda.empty_cache()
         line["batched"] = bench_batch(args, dpo, torch)
         line["serving"] = bench_serve(args, dpo, torch)
@@ -590,7 +769,8 @@ def bench_batch(args, dpo, torch, full_line=False):
         f"({time.time() - t0:.1f}s)")
     base = dpo.Options(threshold=32, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
                        steps_per_replay=16, child_block=128)
-    tuned, traces = autotune.tune("bfs", da, graphs, queries, bucket, 3, base, max_runs=8, log=log)
+    tuned, traces, gtrace = autotune.tune("bfs", da, graphs, queries, bucket, 3, base, max_runs=8,
+                                          log=log)
     qs = [(g, s, bucket[g]) for g, s in queries]
     tot, slot0 = dpo.dpo_batch_slots(da, qs)
     out = torch.empty(tot, dtype=torch.int32, device="cuda")
@@ -620,7 +800,10 @@ def bench_batch(args, dpo, torch, full_line=False):
            "gteps": round(edges / 2 / (ms * 1e-3) / 1e9, 3), "queries": len(qs),
            "levels": st["levels"],
            "tuned": [o.label() for o in tuned],
-           "tuning_runs": [len(t) for t in traces]}
+           "tuning_runs": [len(t) for t in traces],
+           "tuning_trace": {"threshold_coarsening_per_bucket": [
+                                {lbl: round(v * 1e3, 3) for lbl, v in t} for t in traces],
+                            "granularity_ms": {lbl: round(v * 1e3, 3) for lbl, v in gtrace}}}
     # a sample of the same queries, one dpo_bfs call each on its own graph
     one = dpo.Options(threshold=32, coarsen=1, steps_per_replay=16, child_block=128)
     sub = qs[::8]
@@ -647,6 +830,8 @@ def bench_batch(args, dpo, torch, full_line=False):
     ev1.record()
     torch.cuda.synchronize()
     res["untuned_ms_per_batch"] = round(ev0.elapsed_time(ev1), 3)
+    res["untuned"] = base.label()
+    res["tuned_speedup_vs_untuned"] = round(res["untuned_ms_per_batch"] / res["ms_per_batch"], 3)
     log(f"[batch] {res}")
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_batch(graphs, queries)
@@ -660,19 +845,76 @@ def bench_batch(args, dpo, torch, full_line=False):
     return res
 
 
-def cpu_batch(graphs, queries, sample=64):
-    """Oracle BFS of a sample of the batch's queries on a pool of host threads."""
+def host_threads():
+    """Oracle pool size: the cores this process may use, at most 16 (one GPU's
+    share of the host)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_batch(graphs, queries, min_seconds=5.0):
+    """Oracle BFS of the batch's queries on a pool of host threads, all 512
+    in order, repeated until at least min_seconds."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
-    nthreads = os.cpu_count() or 1
-    sub = queries[::max(1, len(queries) // sample)]
+    nthreads = host_threads()
+    done, rounds = 0, 0
     t0 = time.perf_counter()
     with ThreadPoolExecutor(nthreads) as ex:
-        list(ex.map(lambda q: oracle.bfs(graphs[q[0]], q[1]), sub))
-    dt = time.perf_counter() - t0
-    return {"value": round(len(sub) / dt, 1), "unit": "traversals/s", "cores": nthreads,
-            "kind": "oracle", "sample": f"{len(sub)} of {len(queries)} queries, queue BFS, "
-                                        f"{nthreads} threads, {dt:.2f} s"}
+        while True:
+            list(ex.map(lambda q: oracle.bfs(graphs[q[0]], q[1]), queries))
+            done += len(queries)
+            rounds += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_seconds:
+                break
+    return {"value": round(done / dt, 1), "unit": "traversals/s", "cores": nthreads,
+            "kind": "oracle", "host": host_cpu(),
+            "sample": f"all {len(queries)} queries x {rounds} round(s), queue BFS, "
+                      f"{nthreads} threads, {dt:.2f} s"}
+
+
+def cpu_serve(graphs, pools, lam, nq, serve_seconds):
+    """The oracle as a server: a pool of host threads takes the queries of the
+    GPU run's Poisson trace for offered rate lam (same seed, kinds, graphs and
+    sources) at their arrival times; latency = completion - arrival.  Only the
+    first nq arrivals are served (a bounded sample: the pool saturates far
+    below the GPU's rates, so the backlog and the latencies grow with it)."""
+    import threading
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(7 + lam)
+    total = max(50, min(int(lam * serve_seconds), 25000))
+    arr = np.cumsum(rng.exponential(1.0 / lam, size=total))
+    kinds = np.where(rng.random(total) < 0.7, "bfs", "sssp")
+    gsel = rng.integers(0, len(graphs), size=total)
+    ssel = rng.integers(0, 64, size=total)
+    nthreads = host_threads()
+    lat = np.full(nq, np.nan)
+    lock = threading.Lock()
+
+    def job(i, t_start):
+        g, s = int(gsel[i]), int(pools[gsel[i]][ssel[i]])
+        if kinds[i] == "bfs":
+            oracle.bfs(graphs[g], s)
+        else:
+            oracle.dijkstra(graphs[g], s)
+        with lock:
+            lat[i] = time.perf_counter() - t_start - arr[i]
+
+    t_start = time.perf_counter()
+    with ThreadPoolExecutor(nthreads) as ex:
+        for i in range(nq):
+            wait = arr[i] - (time.perf_counter() - t_start)
+            if wait > 0:
+                time.sleep(wait)
+            ex.submit(job, i, t_start)
+    wall = time.perf_counter() - t_start
+    return {"value": round(nq / wall, 1), "unit": "q/s", "cores": nthreads, "kind": "oracle",
+            "host": host_cpu(), "offered_qps": lam,
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "sample": f"first {nq} arrivals of the offered-{lam} q/s trace (70/30 queue BFS / "
+                      f"binary-heap Dijkstra), {nthreads} threads, {wall:.2f} s"}
 
 
 # ---------------------------------------------------------------- serving
@@ -740,6 +982,10 @@ def bench_serve(args, dpo, torch, full_line=False):
         log(f"[serve] {r}")
     for e in engines.values():
         e.close()
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_serve(graphs, pools, rates[0], args.cpu_serve_queries, args.serve_seconds)
+        log(f"[serve] oracle pool: {cpu}")
     if full_line:
         best = max(results, key=lambda r: r["achieved_qps"])
         return {"metric": "serving q/s and p99 latency (BFS/SSSP 70/30, 8 resident R-MAT graphs)",
@@ -747,10 +993,11 @@ def bench_serve(args, dpo, torch, full_line=False):
                 "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
                 "vs_baseline": None, "dtype": "int32", "data": "synthetic",
                 "config": {"workload": "Poisson BFS/SSSP 70/30, scales 14..20 + second 20"},
-                "serving": results}
+                "serving": results, "cpu_baseline": cpu}
     return {"rates": results, "graphs": "R-MAT scales 14..20 + second 20, ef 16",
             "mix": "70% BFS / 30% SSSP", "steps_per_replay": 4, "max_slots": max_slots,
-            "thresholds": {k: opts(k)[0].threshold for k in engines}}
+            "serve_seconds": args.serve_seconds,
+            "thresholds": {k: opts(k)[0].threshold for k in engines}, "cpu_baseline": cpu}
 
 
 # ---------------------------------------------------------------- low nesting
@@ -789,25 +1036,213 @@ def bench_road(args, dpo, torch):
     return {"workload": "road-like grid BFS (low nested parallelism)", **res}
 
 
-def sweep(dpo, torch, wl, dg):
+# ---------------------------------------------------------------- breakdown
+REALTIME_MHZ = 100.0  # the constant-rate clock the timed kernels stamp
+
+
+def phase_split(rows, mhz=REALTIME_MHZ):
+    """Execution-time breakdown of one timed traversal (Sec. VIII-B).
+
+    rows: uint64 [levels, 3 kernels, workgroups, 8] as written by
+    dpo_traverse_timed.  Per level and kernel, the kernel's span (first
+    workgroup entry to last exit) is split among the phases in proportion to
+    the cycles its waves spent in each; the gap from the parent kernel's end to
+    the child kernel's start is launch time too (the aggregated grids start
+    there); every other gap between kernels (including empty kernels, which
+    write no rows) is reported as "gaps".  Returns (totals in us, per-level
+    list of (level, {phase: us}), child-kernel imbalance = time-weighted
+    busiest-workgroup span / mean workgroup span)."""
+    phases = ("parent", "aggregation", "launch", "disaggregation", "child")
+    tot = dict.fromkeys(phases + ("gaps",), 0.0)
+    per_level, prev_end = [], None
+    imb_num = imb_den = 0.0
+    for L in range(rows.shape[0]):
+        lv = dict.fromkeys(phases + ("gaps",), 0.0)
+        kern = {}
+        for k in range(rows.shape[1]):
+            r = rows[L, k]
+            r = r[r[:, 1] != 0]
+            if r.size == 0:
+                continue
+            t0, t1 = int(r[:, 0].min()), int(r[:, 1].max())
+            cyc = r[:, 2:7].astype(np.float64).sum(axis=0)
+            span = (t1 - t0) / mhz
+            share = cyc / cyc.sum() if cyc.sum() > 0 else np.zeros(5)
+            for p, x in zip(phases, share):
+                lv[p] += span * x
+            kern[k] = (t0, t1)
+            if k == 1:
+                wg = (r[:, 1] - r[:, 0]).astype(np.float64) / mhz
+                imb_num += span * wg.max() / max(wg.mean(), 1e-9)
+                imb_den += span
+        if not kern:
+            continue
+        order = sorted(kern.items(), key=lambda kv: kv[1][0])
+        if prev_end is not None:
+            lv["gaps"] += max(0, order[0][1][0] - prev_end) / mhz
+        for (ka, (a0, a1)), (kb, (b0, b1)) in zip(order, order[1:]):
+            gap = max(0, b0 - a1) / mhz
+            lv["launch" if (ka, kb) == (0, 1) else "gaps"] += gap
+        prev_end = order[-1][1][1]
+        per_level.append((L, lv))
+        for p in tot:
+            tot[p] += lv[p]
+    return tot, per_level, (imb_num / imb_den if imb_den else 1.0)
+
+
+def bench_breakdown(args, dpo, torch):
+    """Sec. VIII-B: parent / aggregation / launch / disaggregation / child time
+    per traversal at CF 1, 2, 4, 8 and a few thresholds, from the timed
+    instantiations of the level kernels; writes profiles/<workload>_breakdown.md."""
+    name = args.workload if args.workload in ("bfs22", "sssp21") else "bfs22"
+    wl = Workload(name)
+    dg = dpo.DeviceGraph.from_host(wl.g)
+    tuned = TUNED[name]
+    Ts = (0, 16, 64) if wl.kind == "bfs" else (0, 128, 512)
+    rs, _ = reached_stats(dpo, torch, wl, dg, dpo.Options(**tuned))
+    steps = max(r[2]["levels"] for r in rs) + 1
+    timing = torch.zeros(dpo.TIMING_BYTES // 8, dtype=torch.int64, device="cuda")
+    out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    phases = ("parent", "aggregation", "launch", "disaggregation", "child", "gaps")
+    results = []
+    for CF in (1, 2, 4, 8):
+        for T in Ts:
+            o = dpo.Options(**{**tuned, "threshold": T, "coarsen": CF, "steps_per_replay": steps})
+            pc, _ = measure(dpo, torch, wl, dg, o, 2, 1)
+            ws = dpo.alloc_workspace(dg, o)
+            acc = dict.fromkeys(phases, 0.0)
+            longest, imb, timed_ms = None, [], []
+            for s in wl.sources:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                dpo.dpo_traverse_timed(wl.kind, dg, int(s), o, out, ws, timing)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                timed_ms.append(e0.elapsed_time(e1))
+                rows = timing.cpu().numpy().view(np.uint64).reshape(64, 3, 4096, 8)
+                tot, per_level, ib = phase_split(rows)
+                for p in phases:
+                    acc[p] += tot[p] / len(wl.sources)
+                imb.append(ib)
+                big = max(per_level, key=lambda x: sum(x[1].values()))
+                if longest is None or sum(big[1].values()) > sum(longest[1].values()):
+                    longest = big
+            r = {"threshold": T, "coarsen": CF, "options": o.label(),
+                 "product_ms_per_traversal": round(float(pc.mean()), 4),
+                 "timed_ms_per_traversal": round(float(np.mean(timed_ms)), 4),
+                 "us_per_traversal": {p: round(v, 1) for p, v in acc.items()},
+                 "child_imbalance": round(float(np.mean(imb)), 3),
+                 "longest_level": {"level": longest[0],
+                                   "us": {p: round(v, 1) for p, v in longest[1].items()}}}
+            results.append(r)
+            log(f"[breakdown] {o.label()}: product {r['product_ms_per_traversal']} ms, "
+                f"timed {r['timed_ms_per_traversal']} ms, {r['us_per_traversal']}")
+            del ws
+    cmd = "python3 bench.py " + " ".join(sys.argv[1:])
+    md = [f"# {name}: execution-time breakdown (parent / aggregation / launch / disaggregation / child)",
+          "", f"Workload: {wl.desc}; child block {tuned.get('child_block', 256)}, 4-block "
+          f"aggregation, {steps} level steps per replay, {len(wl.sources)} source(s).", "",
+          f"Command (MI355X, repository root): `{cmd}`", "",
+          "Method: the timed instantiations of the level kernels (dpo_traverse_timed: the same "
+          "kernels and grids as the product ones, with a shader-clock stamp at each phase "
+          "boundary after the wave's outstanding memory operations) give each workgroup's "
+          "cycles per phase and its entry / exit on a 100 MHz clock.  Each kernel's span is "
+          "split among the phases in proportion to the cycles; the gap from the parent "
+          "kernel's end to the child kernel's start is launch time (the aggregated grids "
+          "start there); other gaps between kernels (including child kernels of levels with "
+          "no launch, which stamp nothing) are gaps.  Phases: parent = frontier reads, "
+          "threshold decisions and the thresholded children run in the parent kernel(s); "
+          "aggregation = scans, launch records and group counters; launch = publishing grids "
+          "and reading the level's published grids, plus the parent-to-child gap; "
+          "disaggregation = finding each wave's first record and loading record windows; "
+          "child = the coarsening loop and the child body.  The stamps wait for memory, so "
+          "the timed traversal is slower than the product one (both columns shown); the "
+          "phase split is of the timed run.", "",
+          "## Mean per traversal (us)", "",
+          "| T | CF | product ms | timed ms | parent | aggregation | launch | disaggregation | child | gaps | child imbalance |",
+          "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in results:
+        u = r["us_per_traversal"]
+        md.append(f"| {r['threshold']} | {r['coarsen']} | {r['product_ms_per_traversal']:.3f} | "
+                  f"{r['timed_ms_per_traversal']:.3f} | " +
+                  " | ".join(f"{u[p]:.1f}" for p in phases) + f" | {r['child_imbalance']:.2f} |")
+    md += ["", "child imbalance: time-weighted ratio of the busiest child workgroup's span to the "
+           "mean workgroup span.", "", "## Longest level of any source (us)", "",
+           "| T | CF | level | parent | aggregation | launch | disaggregation | child | gaps |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for r in results:
+        u = r["longest_level"]["us"]
+        md.append(f"| {r['threshold']} | {r['coarsen']} | {r['longest_level']['level']} | " +
+                  " | ".join(f"{u[p]:.1f}" for p in phases) + " |")
+    outp = os.path.join(ROOT, "profiles", f"{name}_breakdown.md")
+    with open(outp, "w") as f:
+        f.write("\n".join(md) + "\n")
+    log(f"[breakdown] wrote {outp}")
+    return {"workload": wl.desc, "breakdown": results}
+
+
+def sweep(dpo, torch, wl, dg, cmd):
     """Sweep of T x CF x granularity (and the aggregation threshold), plus flat
-    and naive, on the workload's graph and sources (JSON lines)."""
+    and naive, on the workload's graph and sources, at its tuned child block
+    size (and SSSP's one-copy threshold).  Prints one JSON line per point and
+    writes profiles/<workload>_sweep.md."""
     import itertools
-    rs, _ = reached_stats(dpo, torch, wl, dg, dpo.Options())
+    import platform
+    tuned = TUNED[wl.name]
+    fixed = {k: tuned[k] for k in ("child_block", "split_min") if k in tuned}
+    rs, _ = reached_stats(dpo, torch, wl, dg, dpo.Options(**{**tuned, "steps_per_replay": 0}))
     edges = float(sum(r[0] for r in rs) / 2)
     steps = max(r[2]["levels"] for r in rs) + 1
-    grid = [dpo.Options.flat(), dpo.Options.naive()]
-    for T, CF, (agg, k) in itertools.product([0, 8, 16, 32, 64, 128, 512], [1, 2, 4, 8],
-                                             [(1, 4), (2, 4), (3, 4), (3, 16), (4, 4)]):
-        grid.append(dpo.Options(threshold=T, coarsen=CF, agg=agg, agg_blocks=k))
-    for T, agg, at in itertools.product([8, 32], [1, 2], [8, 32]):  # aggregation threshold
-        grid.append(dpo.Options(threshold=T, coarsen=1, agg=agg, agg_threshold=at))
-    for o in grid:
+    grans = [(1, 4, "wave"), (2, 4, "block"), (3, 4, "4-block"), (3, 16, "16-block"), (4, 4, "grid")]
+    grid = [("flat", "-", "-", dpo.Options.flat()),
+            ("naive", 0, 1, dpo.Options.naive(child_block=fixed.get("child_block", 256)))]
+    for T, CF, (agg, k, gname) in itertools.product([0, 8, 16, 32, 64, 128, 512, 2048],
+                                                    [1, 2, 4, 8], grans):
+        grid.append((gname, T, CF, dpo.Options(threshold=T, coarsen=CF, agg=agg, agg_blocks=k,
+                                               **fixed)))
+    for T, (agg, gname), at in itertools.product([8, 32], [(1, "wave"), (2, "block")], [8, 32]):
+        grid.append((f"{gname} A{at}", T, 1, dpo.Options(threshold=T, coarsen=1, agg=agg,
+                                                         agg_threshold=at, **fixed)))
+    rows = []
+    for gname, T, CF, o in grid:
         o.steps_per_replay = steps
         pc, _ = measure(dpo, torch, wl, dg, o, 2, 1)
         g = 2 * edges / (pc.sum() * 1e-3) / 1e9
+        rows.append((g, gname, T, CF, o.label(), float(pc.mean())))
         print(json.dumps({"options": o.label(), "gteps": round(g, 3),
                           "ms_per_traversal": round(float(pc.mean()), 4)}), flush=True)
+    nested = [r for r in rows if r[1] not in ("flat", "naive")]
+    best = max(nested)
+    md = [f"# {wl.name}: threshold x coarsening x granularity sweep", "",
+          f"Workload: {wl.desc} (n = {wl.g.n}, m = {wl.g.m}).  Child block {fixed.get('child_block', 256)}"
+          f"{', one visited copy below ' + str(fixed['split_min']) + ' frontier entries' if 'split_min' in fixed else ''}; "
+          f"{steps} level steps per replay; each point 1 warm-up + 2 timed passes over the "
+          f"{len(wl.sources)} source(s), hipEvents around each call.  GTEPS = undirected edges "
+          f"in the reached components / time.", "",
+          f"Command (MI355X, repository root): `{cmd}`", "",
+          f"Best nested point: **{best[4]}, {best[0]:.2f} GTEPS** ({best[5]:.3f} ms per traversal); "
+          f"flat {rows[0][0]:.3f}, naive {rows[1][0]:.3f} GTEPS.", "",
+          "## Best point per granularity", "", "| granularity | best options | GTEPS |", "|---|---|---|"]
+    for gname in [g[2] for g in grans] + ["wave A8", "wave A32", "block A8", "block A32"]:
+        cand = [r for r in nested if r[1] == gname]
+        if cand:
+            b = max(cand)
+            md.append(f"| {gname} | {b[4]} | {b[0]:.2f} |")
+    md += ["", "## Best point per coarsening factor", "", "| CF | best options | GTEPS |", "|---|---|---|"]
+    for CF in (1, 2, 4, 8):
+        b = max(r for r in nested if r[3] == CF)
+        md.append(f"| {CF} | {b[4]} | {b[0]:.2f} |")
+    md += ["", "## Best point per threshold", "", "| T | best options | GTEPS |", "|---|---|---|"]
+    for T in (0, 8, 16, 32, 64, 128, 512, 2048):
+        b = max(r for r in nested if r[2] == T)
+        md.append(f"| {T} | {b[4]} | {b[0]:.2f} |")
+    md += ["", "## Every point", "", "| options | GTEPS | ms / traversal |", "|---|---|---|"]
+    md += [f"| {r[4]} | {r[0]:.3f} | {r[5]:.4f} |" for r in sorted(rows, reverse=True)]
+    out = os.path.join(ROOT, "profiles", f"{wl.name}_sweep.md")
+    with open(out, "w") as f:
+        f.write("\n".join(md) + "\n")
+    log(f"[sweep] wrote {out} (host {platform.node()})")
 
 
 if __name__ == "__main__":

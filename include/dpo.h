@@ -26,7 +26,7 @@
  *   - Work is enqueued on `stream`.  The traversal calls synchronise `stream`
  *     once per `steps_per_replay` level steps to read the done flag, so they
  *     return only when the traversal has finished and outputs are final.
- * *   - Errors are return codes, never exceptions.  Argument errors are found on
+ *   - Errors are return codes, never exceptions.  Argument errors are found on
  *     the host before anything is enqueued.  Device-detected errors (queue
  *     capacity, a vertex id out of range) are read back at the end of the
  *     call.
@@ -153,6 +153,32 @@ dpo_status dpo_bfs(const dpo_csr* g, int32_t source, const dpo_options* o, int32
  * 0xFFFFFFFF or more).  Other arguments as for dpo_bfs. */
 dpo_status dpo_sssp(const dpo_csr* g, int32_t source, const dpo_options* o, uint32_t* dist,
                     void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
+
+/* ------------------------------------------------------------ phase timing
+ * Execution-time breakdown of one traversal (Sec. VIII-B splits time into
+ * parent work, aggregation, launch, disaggregation and child work).  Runs
+ * dpo_bfs (kind 0) or dpo_sssp (kind 1) with timed instantiations of the
+ * level kernels, on the same grids, so with the same schedule and results.
+ * Each wave stamps a shader-clock counter at phase boundaries, after waiting
+ * for its own outstanding memory operations (so the timed traversal is
+ * slower than the product one), and each workgroup of each level kernel
+ * writes one row of 8 uint64 words to `timing` (device, caller-owned, at
+ * least DPO_TIMING_BYTES, zeroed by the call) at index
+ *   ((level * 3 + kernel) * 4096 + workgroup) * 8,
+ * kernel 0 = parent kernel, 1 = child kernel, 2 = SSSP's thresholded-children
+ * kernel; words: [0] a constant-rate (100 MHz) clock at the workgroup's entry,
+ * [1] at its exit, [2..6] the cycles its waves spent in parent work,
+ * aggregation, launch (publishing a grid; reading the level's published
+ * grids), disaggregation (finding records, loading record windows) and child
+ * work, summed over its waves, [7] the largest total of one wave.  A row of
+ * zeros: the workgroup did not run (or the level index is 64 or more).
+ * Counters are not collected.  Otherwise as dpo_bfs / dpo_sssp;
+ * DPO_ERR_ARG if kind, timing or timing_bytes are invalid. */
+#define DPO_TIMING_BYTES (64u * 3u * 4096u * 8u * 8u)
+
+dpo_status dpo_traverse_timed(int32_t kind, const dpo_csr* g, int32_t source, const dpo_options* o,
+                              void* out, void* ws, size_t ws_bytes, void* stream, void* timing,
+                              size_t timing_bytes);
 
 /* ------------------------------------------------------------------ batches
  * Many traversals in one launch sequence (the parent and child kernels of a

@@ -136,9 +136,11 @@ def simulate_nested(row_ptr, frontier, threshold: int, child_block: int, coarsen
                     group_parents: int):
     """One level of the transformed nested schedule, walked in pure Python.
 
-    Returns (serial, child): ``serial`` lists (parent, edge) pairs run inside
-    the parent thread, ``child`` lists (parent, edge) pairs run by aggregated,
-    coarsened child blocks.  Steps, in the order Sec. VI applies them:
+    Returns (serial, child, grids): ``serial`` lists (parent, edge) pairs run
+    inside the parent thread, ``child`` lists (parent, edge) pairs run by
+    aggregated, coarsened child blocks, ``grids`` lists (records, blocks) of
+    each aggregated grid launched (a group with at least one launching
+    parent).  Steps, in the order Sec. VI applies them:
 
       thresholding (Sec. III-B): deg < T -> serial loop over the child
         threads in the parent; otherwise a launch of gDim = ceil(deg/bDim)
@@ -153,7 +155,7 @@ def simulate_nested(row_ptr, frontier, threshold: int, child_block: int, coarsen
     Small inputs only (tests).
     """
     rp = [int(x) for x in row_ptr]
-    serial, child = [], []
+    serial, child, grids = [], [], []
     for g0 in range(0, len(frontier), group_parents):
         group = [int(u) for u in frontier[g0:g0 + group_parents]]
         records, scanned, total = [], [], 0
@@ -173,6 +175,8 @@ def simulate_nested(row_ptr, frontier, threshold: int, child_block: int, coarsen
             records.append((u, rp[u], deg, gdim))
             scanned.append(total)
             total += cgdim
+        if records:
+            grids.append((len(records), total))
         for blk in range(total):
             lo, hi = 0, len(scanned)          # upper bound of blk in scanned
             while lo < hi:
@@ -192,4 +196,4 @@ def simulate_nested(row_ptr, frontier, threshold: int, child_block: int, coarsen
                     i = ob * child_block + t
                     if i < deg:
                         child.append((u, start + i))
-    return serial, child
+    return serial, child, grids

@@ -1,15 +1,25 @@
-"""Per-size-bucket tuning of threshold and coarsening for batched traversals.
+"""Tuning of threshold, coarsening and aggregation granularity for batched
+traversals.
 
 Sec. VIII-C of the paper reports that the best threshold is usually the one
 that leaves about 6,000-8,000 child-grid launches, that performance is not
 sensitive to the coarsening factor once it is large enough, that warp
 granularity is never the best, and that a handful of runs finds a point close
-to the best.  The tuner follows that: for each bucket it starts from the
-threshold whose launch count (parents of degree >= T, summed over the bucket's
-queries) is closest to the 6,000-8,000 band, then takes greedy steps through a
-small (T, CF) grid, timing the batch restricted to that bucket, and stops when
-no neighbour is faster or after `max_runs` timed points.  The result can be
-saved as JSON and reloaded, so a tuned table is reused across runs.
+to the best.  The tuner follows that in two stages:
+
+1. per size bucket, threshold and coarsening: start from the threshold whose
+   launch count (parents of degree >= T, summed over the bucket's queries) is
+   closest to the 6,000-8,000 band, then take greedy steps through a small
+   (T, CF) grid, timing the batch restricted to that bucket, until no
+   neighbour is faster or after `max_runs` timed points;
+2. aggregation granularity, for the whole launch: block, 4-block, 16-block
+   and grid (wave is skipped, as the paper finds it never best), timing the
+   whole batch with every bucket at its stage-1 point.
+
+Granularity is a property of the launch, not of a bucket: the parent
+workgroups' frontier entries mix queries of every bucket, and aggregation
+groups are formed over those entries.  The result can be saved as JSON and
+reloaded, so a tuned table is reused across runs.
 """
 from __future__ import annotations
 
@@ -44,22 +54,48 @@ def heuristic_threshold(graphs, queries) -> int:
     return min(T_GRID, key=lambda T: abs(np.log((counts[T] + 1) / target)))
 
 
+GRANULARITIES = ((dpo.DPO_AGG_BLOCK, 4, "block"), (dpo.DPO_AGG_MULTIBLOCK, 4, "4-block"),
+                 (dpo.DPO_AGG_MULTIBLOCK, 16, "16-block"), (dpo.DPO_AGG_GRID, 4, "grid"))
+
+
 def _time_batch(kind, arena, queries, opts, reps=2):
+    """Best of `reps` wall times of one batch call; `opts` is one Options (every
+    query in bucket 0) or a per-bucket list."""
     import torch
+    bopts = opts if isinstance(opts, (list, tuple)) else [opts]
     tot, _ = dpo.dpo_batch_slots(arena, queries)
     out = torch.empty(tot, dtype=torch.int32, device="cuda")
-    ws = torch.empty(dpo.dpo_batch_workspace_bytes(arena, queries, opts), dtype=torch.uint8,
+    ws = torch.empty(dpo.dpo_batch_workspace_bytes(arena, queries, bopts[0]), dtype=torch.uint8,
                      device="cuda")
     f = dpo.dpo_bfs_batch if kind == "bfs" else dpo.dpo_sssp_batch
-    f(arena, queries, [opts], out, ws)  # warm-up (also instantiates the graph)
+    f(arena, queries, bopts, out, ws)  # warm-up (also instantiates the graph)
     torch.cuda.synchronize()
     best = float("inf")
     for _ in range(reps):
         t0 = time.perf_counter()
-        f(arena, queries, [opts], out, ws)
+        f(arena, queries, bopts, out, ws)
         torch.cuda.synchronize()
         best = min(best, time.perf_counter() - t0)
     return best
+
+
+def with_granularity(o: dpo.Options, agg: int, k: int) -> dpo.Options:
+    return dpo.Options(**{**asdict(o), "agg": agg, "agg_blocks": k})
+
+
+def tune_granularity(kind, arena, queries, bucket_opts, log=None, reps=3):
+    """Stage 2: times the whole batch (queries with their buckets) at each
+    granularity, every bucket keeping its threshold and coarsening.  Returns
+    (per-bucket Options at the fastest granularity, [(label, seconds)])."""
+    trace = []
+    for agg, k, name in GRANULARITIES:
+        cand = [with_granularity(o, agg, k) for o in bucket_opts]
+        t = _time_batch(kind, arena, queries, cand, reps)
+        trace.append((name, t, cand))
+        if log:
+            log(f"[tune] {kind} granularity {name}: {t * 1e3:.3f} ms")
+    name, t, best = min(trace, key=lambda x: x[1])
+    return best, [(n, v) for n, v, _ in trace]
 
 
 def tune_bucket(kind, arena, graphs, queries, base: dpo.Options, max_runs: int = 10, log=None):
@@ -96,7 +132,9 @@ def tune_bucket(kind, arena, graphs, queries, base: dpo.Options, max_runs: int =
 
 def tune(kind, arena, graphs, queries, bucket_of_graph, nbuckets, base: dpo.Options,
          max_runs: int = 10, log=None):
-    """Tunes every bucket; returns the per-bucket Options list and the traces."""
+    """Tunes every bucket's threshold and coarsening (stage 1), then the
+    launch's aggregation granularity (stage 2).  Returns the per-bucket Options
+    list, the per-bucket (T, CF) traces and the granularity trace."""
     opts, traces = [], []
     for b in range(nbuckets):
         qb = [(g, s) for g, s in queries if bucket_of_graph[g] == b]
@@ -107,7 +145,9 @@ def tune(kind, arena, graphs, queries, bucket_of_graph, nbuckets, base: dpo.Opti
         o, tr = tune_bucket(kind, arena, graphs, qb, base, max_runs, log)
         opts.append(o)
         traces.append(tr)
-    return opts, traces
+    qs = [(g, s, bucket_of_graph[g]) for g, s in queries]
+    opts, gtrace = tune_granularity(kind, arena, qs, opts, log)
+    return opts, traces, gtrace
 
 
 def save(path, opts, meta=None):

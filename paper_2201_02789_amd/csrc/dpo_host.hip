@@ -134,6 +134,8 @@ struct GridEntry {
   unsigned third;
 };
 
+constexpr int kMaxGridEntries = 64;
+
 struct Runtime {
   std::mutex mu;
   std::vector<CachedGraph> graphs;
@@ -143,7 +145,10 @@ struct Runtime {
   Query* host_q = nullptr;                   // pinned: MAX_QUERIES query records
   int32_t* host_list = nullptr;              // pinned: MAX_QUERIES query indices + prefix
   int cu_count = 0;
-  std::vector<GridEntry> grids;
+  // persistent grid sizes per kernel (fixed storage: the no-allocation entry
+  // point uses them too)
+  GridEntry grids[kMaxGridEntries];
+  int ngrids = 0;
 };
 
 Runtime& rt() {
@@ -153,12 +158,19 @@ Runtime& rt() {
 
 dpo_status hip_ok(hipError_t e) { return e == hipSuccess ? DPO_OK : DPO_ERR_HIP; }
 
-dpo_status ensure_runtime(Runtime& r) {
-  if (r.host_flags) return DPO_OK;
+// Compute-unit count of the current device (no allocation).
+dpo_status ensure_device(Runtime& r) {
+  if (r.cu_count > 0) return DPO_OK;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return DPO_ERR_HIP;
   if (hipDeviceGetAttribute(&r.cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return DPO_ERR_HIP;
+  return DPO_OK;
+}
+
+dpo_status ensure_runtime(Runtime& r) {
+  if (r.host_flags) return DPO_OK;
+  if (ensure_device(r) != DPO_OK) return DPO_ERR_HIP;
   void* p = nullptr;
   const size_t qbytes = (size_t)MAX_QUERIES * (sizeof(Query) + 8) + 4;
   if (hipHostMalloc(&p, 256 + (size_t)MAX_GRID * NSTAT * 8 + qbytes, hipHostMallocDefault) !=
@@ -173,8 +185,8 @@ dpo_status ensure_runtime(Runtime& r) {
 
 // Persistent grid: as many workgroups as can be resident at once.
 int persistent_grid(Runtime& r, const void* kernel, unsigned shmem = 0) {
-  for (auto& e : r.grids)
-    if (e.first == kernel && e.third == shmem) return e.second;
+  for (int i = 0; i < r.ngrids; ++i)
+    if (r.grids[i].first == kernel && r.grids[i].third == shmem) return r.grids[i].second;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, PB, shmem) != hipSuccess ||
       per_cu < 1)
@@ -182,7 +194,7 @@ int persistent_grid(Runtime& r, const void* kernel, unsigned shmem = 0) {
   if (per_cu > 8) per_cu = 8;
   int grid = per_cu * r.cu_count;
   if (grid > MAX_GRID) grid = MAX_GRID;
-  r.grids.push_back(GridEntry{kernel, grid, shmem});
+  if (r.ngrids < kMaxGridEntries) r.grids[r.ngrids++] = GridEntry{kernel, grid, shmem};
   return grid;
 }
 
@@ -271,9 +283,12 @@ struct SetRun {
   int32_t* qlist = nullptr;  // device: indices of the queries being admitted
 };
 
+// tm: phase-timing rows; non-null selects the timed instantiations of the
+// level kernels, run at the grid sizes of the product ones (same schedule).
 dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_options& o,
                        int64_t slots, int32_t nq, void* out, void* ws, size_t ws_bytes,
-                       void* stream, bool count_stats, SetRun* sr) {
+                       void* stream, bool count_stats, SetRun* sr,
+                       unsigned long long* tm = nullptr) {
   if (slots < 1 || slots > INT32_MAX || nq < 1 || nq > MAX_QUERIES) return DPO_ERR_ARG;
   const Layout lay = layout_for(slots, nq, o);
   if (ws_bytes < lay.total) return DPO_ERR_WORKSPACE;
@@ -329,6 +344,12 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   sr->cgrid = sr->child ? persistent_grid(r, sr->child) : 0;
   sr->steps = o.steps_per_replay ? o.steps_per_replay : kDefaultSteps;
   sr->stream = (hipStream_t)stream;
+  if (tm) {
+    sr->parent = parent_kernel_ptr(problem, gran, true);
+    sr->child = sr->child ? child_kernel_ptr(problem, true) : nullptr;
+    sr->serial = serial_kernel_ptr(problem, gran, true);
+    a.tm = tm;
+  }
   return DPO_OK;
 }
 
@@ -446,7 +467,8 @@ dpo_status read_stats(Runtime& r, SetRun& sr, dpo_stats* st) {
 }
 
 dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_options* o,
-                    void* out, void* ws, size_t ws_bytes, void* stream, dpo_stats* st) {
+                    void* out, void* ws, size_t ws_bytes, void* stream, dpo_stats* st,
+                    unsigned long long* tm = nullptr) {
   if (!o || !out || !ws) return DPO_ERR_ARG;
   dpo_status s = check_graph(g, problem == PROB_SSSP);
   if (s != DPO_OK) return s;
@@ -459,8 +481,10 @@ dpo_status traverse(int problem, const dpo_csr* g, int32_t source, const dpo_opt
   s = ensure_runtime(r);
   if (s != DPO_OK) return s;
   SetRun sr;
-  s = prepare_set(r, problem, g, *o, round32(g->n), 1, out, ws, ws_bytes, stream, st != nullptr, &sr);
+  s = prepare_set(r, problem, g, *o, round32(g->n), 1, out, ws, ws_bytes, stream, st != nullptr, &sr,
+                  tm);
   if (s != DPO_OK) return s;
+  if (tm && hipMemsetAsync(tm, 0, DPO_TIMING_BYTES, sr.stream) != hipSuccess) return DPO_ERR_HIP;
   Query* hq = r.host_q;
   hq[0] = Query{0, g->n, 0, 0, o->threshold, o->coarsen, 0, source};
   int32_t* hl = r.host_list;
@@ -870,6 +894,15 @@ dpo_status dpo_bfs(const dpo_csr* g, int32_t source, const dpo_options* o, int32
 dpo_status dpo_sssp(const dpo_csr* g, int32_t source, const dpo_options* o, uint32_t* dist,
                     void* ws, size_t ws_bytes, void* stream, dpo_stats* st) {
   return dpo::traverse(dpo::PROB_SSSP, g, source, o, dist, ws, ws_bytes, stream, st);
+}
+
+dpo_status dpo_traverse_timed(int32_t kind, const dpo_csr* g, int32_t source, const dpo_options* o,
+                              void* out, void* ws, size_t ws_bytes, void* stream, void* timing,
+                              size_t timing_bytes) {
+  if ((kind != 0 && kind != 1) || !timing || timing_bytes < (size_t)DPO_TIMING_BYTES)
+    return DPO_ERR_ARG;
+  return dpo::traverse(kind == 0 ? dpo::PROB_BFS : dpo::PROB_SSSP, g, source, o, out, ws, ws_bytes,
+                       stream, nullptr, (unsigned long long*)timing);
 }
 
 const char* dpo_strerror(int32_t status) {

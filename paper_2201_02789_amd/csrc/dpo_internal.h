@@ -28,6 +28,19 @@ enum { AGG_NONE = 0, AGG_WAVE = 1, AGG_BLOCK = 2, AGG_MULTI = 3, AGG_FLAT = 4 };
 enum { ERR_ARG = 1, ERR_CAPACITY = 4, ERR_TIMEOUT = 5 };
 enum { S_FRONT = 0, S_SERIAL, S_REC, S_CHILD, S_ESER, S_ECHILD, S_DESC };
 
+// Phase timing (the timed instantiations of the level kernels only).  Each
+// workgroup of each level kernel writes one row of TM_ROW words at
+// tm[((level * TM_KINDS + kind) * MAX_GRID + workgroup) * TM_ROW]:
+//   [0] realtime clock at entry, [1] at exit (constant-rate counter),
+//   [2 + p] shader-clock cycles its waves spent in phase p (summed over the
+//   workgroup's waves), [7] the largest total of one wave.
+// Rows of levels >= TM_LEVELS are not written.
+constexpr int TM_LEVELS = 64;
+constexpr int TM_KINDS = 3;  // parent kernel, child kernel, thresholded-children kernel
+constexpr int TM_ROW = 8;
+enum { TK_PARENT = 0, TK_CHILD = 1, TK_SERIAL = 2 };
+enum { TP_PARENT = 0, TP_AGG, TP_LAUNCH, TP_DISAGG, TP_CHILD, TP_N };
+
 // Counters of one level; three sets rotate by level % 3 so that the parent
 // kernel of level L can clear the set of level L + 1 while nobody uses it.
 struct LevelSet {
@@ -87,6 +100,7 @@ struct Args {
   int4* desc;                      // [NQD][desc_cap] {record base, records, block base, -}
   unsigned long long* stats;       // [MAX_GRID][NSTAT], one row per workgroup
   uint32_t* sercnt;                // [MAX_GRID] listed thresholded parents per workgroup
+  unsigned long long* tm;          // phase-timing rows (timed kernels only)
   int32_t slots;                   // total output slots (sum of the queries' n)
   int32_t m;                       // CSR arena entries
   int32_t nq;
@@ -106,9 +120,10 @@ struct Args {
   int32_t pad2;
 };
 
-const void* parent_kernel_ptr(int problem, int gran);
-const void* child_kernel_ptr(int problem);
-const void* serial_kernel_ptr(int problem, int gran);
+// timed: the instantiation that stamps its phases into Args::tm
+const void* parent_kernel_ptr(int problem, int gran, bool timed = false);
+const void* child_kernel_ptr(int problem, bool timed = false);
+const void* serial_kernel_ptr(int problem, int gran, bool timed = false);
 const void* init_kernel_ptr(int problem);
 const void* admit_kernel_ptr(int problem);
 const void* admit_sources_kernel_ptr();

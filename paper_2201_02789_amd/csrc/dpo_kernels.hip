@@ -341,6 +341,62 @@ __device__ __forceinline__ void add_stats(const Args& a, unsigned long long* s_s
   if (tid < NSTAT && blockIdx.x < MAX_GRID) a.stats[blockIdx.x * NSTAT + tid] += s_stats[tid];
 }
 
+// Phase clock of one wave, for the timed instantiations (ON = false: empty).
+// mark(p) charges the shader-clock cycles since the previous mark to phase p,
+// after the wave's outstanding memory operations have completed, so each
+// phase pays for the loads and stores it issued.  Marks sit only at points
+// that every lane of the wave reaches together, so the clock values stay
+// wave-uniform.
+template <bool ON>
+struct PhaseClock {
+  uint64_t last = 0;
+  uint64_t acc[TP_N] = {0, 0, 0, 0, 0};
+  __device__ __forceinline__ void start() {
+    if (ON) last = __builtin_amdgcn_s_memtime();
+  }
+  __device__ __forceinline__ void mark(int p) {
+    if (!ON) return;
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint64_t now = __builtin_amdgcn_s_memtime();
+    acc[p] += now - last;
+    last = now;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+};
+
+__device__ __forceinline__ uint64_t realtime() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Timed instantiations: the workgroup's row (entry / exit realtime, cycles per
+// phase summed over its waves, the busiest wave's total).  Block-uniform call.
+template <bool ON>
+__device__ __forceinline__ void tm_write(const Args& a, const PhaseClock<ON>& pc, int kind,
+                                         uint32_t L, uint64_t t_entry, int tid) {
+  if (!ON) return;
+  __shared__ unsigned long long s_tm[NW][TP_N];
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0)
+    for (int p = 0; p < TP_N; ++p) s_tm[wave][p] = pc.acc[p];
+  __syncthreads();
+  if (tid == 0 && L < (uint32_t)TM_LEVELS && blockIdx.x < (uint32_t)MAX_GRID) {
+    unsigned long long sum[TP_N] = {0, 0, 0, 0, 0}, mx = 0;
+    for (int w = 0; w < NW; ++w) {
+      unsigned long long t = 0;
+      for (int p = 0; p < TP_N; ++p) {
+        sum[p] += s_tm[w][p];
+        t += s_tm[w][p];
+      }
+      mx = t > mx ? t : mx;
+    }
+    unsigned long long* row =
+        a.tm + ((size_t)(L * TM_KINDS + (uint32_t)kind) * MAX_GRID + blockIdx.x) * TM_ROW;
+    row[0] = t_entry;
+    row[1] = realtime();
+    for (int p = 0; p < TP_N; ++p) row[2 + p] = sum[p];
+    row[7] = mx;
+  }
+}
+
 // Append one aggregated grid to descriptor queue q (one lane).
 __device__ __forceinline__ void publish(const Args& a, LevelSet* ls, uint32_t q, uint32_t rec_base,
                                         uint32_t nrec, uint32_t total) {
@@ -413,7 +469,7 @@ __device__ __forceinline__ Parent load_parent(const Args& a, const int32_t* fin,
 // workgroup's list length in a.sercnt; PH_SERIAL, launched after the level's
 // child kernel on the same grid, runs pass 2 over that list (SSSP: its parents
 // are then checked against every improvement the launched children made).
-template <int P, int G, int PH>
+template <int P, int G, int PH, bool TM>
 __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_fpre[NQF + 2];
@@ -427,6 +483,10 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
+  uint64_t t_entry = 0;
+  if (TM) t_entry = realtime();
+  PhaseClock<TM> pc;
+  pc.start();
   if (st->done || st->error) return;
   const uint32_t L = st->base + step;
   LevelSet* prv = &st->set[(L + 2) % 3];  // fills of frontier L
@@ -546,38 +606,48 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
             make_int4(start, deg, slot, (int32_t)du);
       }
     }
+    pc.mark(TP_PARENT);
     if (G != AGG_FLAT) {
       if (launch) ++cn.rec;
 
       if (G == AGG_NONE) {
         // every launching parent publishes its own grid; its record sits at
         // its frontier index
+        if (TM) {
+          if (launch) put_record<P>(a, i, start, deg, 0u, du, q, slot);
+          pc.mark(TP_AGG);
+        }
         if (launch) {
-          put_record<P>(a, i, start, deg, 0u, du, q, slot);
+          if (!TM) put_record<P>(a, i, start, deg, 0u, du, q, slot);
           publish(a, cur, vb % NQD, i, 1u, cg);
           ++cn.desc;
         }
+        pc.mark(TP_LAUNCH);
       } else if (G == AGG_WAVE) {
         const unsigned long long m = __ballot(launch);
         const uint32_t nrec = (uint32_t)__popcll(m);
         const uint32_t seg = vb * PB + wave * 64;
         if (m && nrec < (uint32_t)a.agg_threshold) {
           // too few participants (Sec. V-B): each parent launches its own grid
+          if (launch) put_record<P>(a, seg + lane_rank(m), start, deg, 0u, du, q, slot);
+          pc.mark(TP_AGG);
           if (launch) {
-            put_record<P>(a, seg + lane_rank(m), start, deg, 0u, du, q, slot);
             publish(a, cur, vb % NQD, seg + lane_rank(m), 1u, cg);
             ++cn.desc;
           }
+          pc.mark(TP_LAUNCH);
         } else if (m) {  // wave-uniform
           const uint32_t incl = wave_incl_scan(cg, lane);
           const uint32_t total = __shfl(incl, 63, 64);
           if (launch) {
             put_record<P>(a, seg + lane_rank(m), start, deg, incl - cg, du, q, slot);
           }
+          pc.mark(TP_AGG);
           if (lane == 0) {
             publish(a, cur, vb % NQD, seg, nrec, total);
             ++cn.desc;
           }
+          pc.mark(TP_LAUNCH);
         }
       } else {
         // block-level scan of (launch, cg): wave scans, then across waves in LDS
@@ -599,20 +669,24 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
           const uint32_t seg = vb * PB;
           if (nrec_b < (uint32_t)a.agg_threshold) {
             // too few participants (Sec. V-B): each parent launches its own grid
+            const uint32_t r = seg + roff + lane_rank(m);
+            if (launch) put_record<P>(a, r, start, deg, 0u, du, q, slot);
+            pc.mark(TP_AGG);
             if (launch) {
-              const uint32_t r = seg + roff + lane_rank(m);
-              put_record<P>(a, r, start, deg, 0u, du, q, slot);
               publish(a, cur, vb % NQD, r, 1u, cg);
               ++cn.desc;
             }
+            pc.mark(TP_LAUNCH);
           } else {
             if (launch) {
               put_record<P>(a, seg + roff + lane_rank(m), start, deg, coff + incl - cg, du, q, slot);
             }
+            pc.mark(TP_AGG);
             if (tid == 0 && nrec_b) {
               publish(a, cur, vb % NQD, seg, nrec_b, total_b);
               ++cn.desc;
             }
+            pc.mark(TP_LAUNCH);
           }
           __syncthreads();  // s_scan reuse
         } else {  // AGG_MULTI: group of k consecutive virtual blocks (Sec. V-A)
@@ -633,23 +707,27 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
             put_record<P>(a, seg + slot0 + roff + lane_rank(m), start, deg, off0 + coff + incl - cg,
                           du, q, slot);
           }
+          // the group's last block to finish "launches" the aggregated grid;
+          // its packed-counter add returned before this increment was issued
+          bool last_block = false;
           if (tid == 0) {
-            // the group's last block to finish "launches" the aggregated grid;
-            // its packed-counter add returned before this increment was issued
             const uint32_t in_group = min((uint32_t)a.k, nvb - g * (uint32_t)a.k);
-            const uint32_t done = atomicAdd(gd, 1u);
-            if (done == in_group - 1) {
-              const unsigned long long tot = atomicAdd(gp, 0ull);
-              const uint32_t nrec_g = (uint32_t)(tot >> 32);
-              if (nrec_g) {
-                publish(a, cur, g % NQD, seg, nrec_g, (uint32_t)tot);
-                ++cn.desc;
-              }
+            last_block = atomicAdd(gd, 1u) == in_group - 1;
+          }
+          pc.mark(TP_AGG);
+          if (last_block) {
+            const unsigned long long tot = atomicAdd(gp, 0ull);
+            const uint32_t nrec_g = (uint32_t)(tot >> 32);
+            if (nrec_g) {
+              publish(a, cur, g % NQD, seg, nrec_g, (uint32_t)tot);
+              ++cn.desc;
             }
           }
+          pc.mark(TP_LAUNCH);
           __syncthreads();  // s_scan / s_bc reuse
         }
       }
+      pc.mark(TP_AGG);
     }
   }
 
@@ -862,6 +940,8 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     for (int i = tid; i < a.nq; i += PB)
       if (s_live[i >> 5] & (1u << (i & 31))) a.q[i].last = (int32_t)L;
   add_stats(a, s_stats, cn, tid);
+  pc.mark(TP_PARENT);
+  tm_write<TM>(a, pc, PH == PH_SERIAL ? TK_SERIAL : TK_PARENT, L, t_entry, tid);
 }
 
 // ------------------------------------------------------------ child kernel
@@ -960,7 +1040,7 @@ __device__ __forceinline__ Window load_window(const Args& a, const uint32_t* cla
 // blocks: the parent of its first block is found by search (the
 // disaggregation of Sec. V-A), then records are taken 64 at a time and their
 // slices U at a time.
-template <int P>
+template <int P, bool TM>
 __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_bc[NW + 8];
@@ -970,6 +1050,10 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   State* st = a.st;
+  uint64_t t_entry = 0;
+  if (TM) t_entry = realtime();
+  PhaseClock<TM> pc;
+  pc.start();
   if (st->done || st->error) return;
   const uint32_t L = st->base + step;
   LevelSet* cur = &st->set[L % 3];
@@ -996,6 +1080,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   const uint32_t t1 = (uint32_t)((uint64_t)(gw + 1) * B / nwaves);
   Counters cn{0, 0, 0, 0, 0, 0, 0};
   Stage s{s_stage[wave], 0u};
+  pc.mark(TP_LAUNCH);  // reading the level's published grids
 
   if (t0 < t1) {
     // disaggregation of the first block (Sec. V-A): queue, descriptor, record
@@ -1012,6 +1097,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
       const uint32_t wn = min(64u, (uint32_t)dd.y - r);
       const Window win = load_window<P>(a, vis.claim, (uint32_t)dd.x + r, wn,
                                         s_qpre[q] + (uint32_t)dd.z, t0, t1, lane, L, cn.child);
+      pc.mark(TP_DISAGG);
       if (win.bad) {
         if (lane == 0) set_error(st, ERR_CAPACITY);
         break;
@@ -1068,6 +1154,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
 #pragma unroll
         for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
       }
+      pc.mark(TP_CHILD);
       if (win.last) break;
       // next window: rest of this descriptor, else the next one (next queue
       // if need be)
@@ -1089,6 +1176,8 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   }
   block_flush(s, a, cur, fout, tid, s_bc);
   add_stats(a, s_stats, cn, tid);
+  pc.mark(TP_CHILD);
+  tm_write<TM>(a, pc, TK_CHILD, L, t_entry, tid);
 }
 
 // ------------------------------------------------------------ init / admit / advance
@@ -1184,35 +1273,44 @@ __global__ void advance_kernel(State* st, uint32_t steps) {
 }
 
 // ---------------------------------------------------------------- tables
-template <int P, int PH>
+template <int P, int PH, bool TM>
 static const void* parent_for(int g) {
   switch (g) {
-    case AGG_NONE: return (const void*)parent_kernel<P, AGG_NONE, PH>;
-    case AGG_WAVE: return (const void*)parent_kernel<P, AGG_WAVE, PH>;
-    case AGG_BLOCK: return (const void*)parent_kernel<P, AGG_BLOCK, PH>;
-    case AGG_MULTI: return (const void*)parent_kernel<P, AGG_MULTI, PH>;
+    case AGG_NONE: return (const void*)parent_kernel<P, AGG_NONE, PH, TM>;
+    case AGG_WAVE: return (const void*)parent_kernel<P, AGG_WAVE, PH, TM>;
+    case AGG_BLOCK: return (const void*)parent_kernel<P, AGG_BLOCK, PH, TM>;
+    case AGG_MULTI: return (const void*)parent_kernel<P, AGG_MULTI, PH, TM>;
     default: return nullptr;
   }
 }
 
+template <bool TM>
+static const void* parent_ptr(int problem, int gran) {
+  if (gran == AGG_FLAT)
+    return problem == PROB_BFS ? (const void*)parent_kernel<PROB_BFS, AGG_FLAT, PH_BOTH, TM>
+                               : (const void*)parent_kernel<PROB_SSSP, AGG_FLAT, PH_BOTH, TM>;
+  return problem == PROB_BFS ? parent_for<PROB_BFS, PH_BOTH, TM>(gran)
+                             : parent_for<PROB_SSSP, PH_LIST, TM>(gran);
+}
+
 // BFS, and the flat kernel: both passes in one kernel.  SSSP with child
 // kernels: pass 1, the child kernel, then pass 2 (serial_kernel_ptr).
-const void* parent_kernel_ptr(int problem, int gran) {
-  if (gran == AGG_FLAT)
-    return problem == PROB_BFS ? (const void*)parent_kernel<PROB_BFS, AGG_FLAT, PH_BOTH>
-                               : (const void*)parent_kernel<PROB_SSSP, AGG_FLAT, PH_BOTH>;
-  return problem == PROB_BFS ? parent_for<PROB_BFS, PH_BOTH>(gran)
-                             : parent_for<PROB_SSSP, PH_LIST>(gran);
+const void* parent_kernel_ptr(int problem, int gran, bool timed) {
+  return timed ? parent_ptr<true>(problem, gran) : parent_ptr<false>(problem, gran);
 }
 
-const void* serial_kernel_ptr(int problem, int gran) {
+const void* serial_kernel_ptr(int problem, int gran, bool timed) {
   if (problem == PROB_BFS || gran == AGG_FLAT) return nullptr;
-  return parent_for<PROB_SSSP, PH_SERIAL>(gran);
+  return timed ? parent_for<PROB_SSSP, PH_SERIAL, true>(gran)
+               : parent_for<PROB_SSSP, PH_SERIAL, false>(gran);
 }
 
-const void* child_kernel_ptr(int problem) {
-  return problem == PROB_BFS ? (const void*)child_kernel<PROB_BFS>
-                             : (const void*)child_kernel<PROB_SSSP>;
+const void* child_kernel_ptr(int problem, bool timed) {
+  if (timed)
+    return problem == PROB_BFS ? (const void*)child_kernel<PROB_BFS, true>
+                               : (const void*)child_kernel<PROB_SSSP, true>;
+  return problem == PROB_BFS ? (const void*)child_kernel<PROB_BFS, false>
+                             : (const void*)child_kernel<PROB_SSSP, false>;
 }
 
 const void* init_kernel_ptr(int) { return (const void*)init_kernel; }

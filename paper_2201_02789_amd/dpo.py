@@ -134,6 +134,11 @@ def lib():
         f.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.POINTER(_Options),
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                       ctypes.POINTER(_Stats)]
+    L.dpo_traverse_timed.restype = ctypes.c_int32
+    L.dpo_traverse_timed.argtypes = [ctypes.c_int32, ctypes.POINTER(_Csr), ctypes.c_int32,
+                                     ctypes.POINTER(_Options), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_size_t]
     L.dpo_batch_slots.restype = ctypes.c_int64
     L.dpo_batch_slots.argtypes = [ctypes.POINTER(_Arena), ctypes.POINTER(_Query), ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -243,6 +248,24 @@ def dpo_sssp(graph: DeviceGraph, source: int, opts: Options, dist, ws, stream=No
              stats: bool = False):
     """dist: int32/uint32 device tensor [n] (written as uint32)."""
     return _traverse(lib().dpo_sssp, "dpo_sssp", graph, source, opts, dist, ws, stream, stats)
+
+
+TIMING_BYTES = 64 * 3 * 4096 * 8 * 8  # DPO_TIMING_BYTES
+TIMING_PHASES = ("parent", "aggregation", "launch", "disaggregation", "child")
+
+
+def dpo_traverse_timed(kind: str, graph: DeviceGraph, source: int, opts: Options, out, ws,
+                       timing, stream=None):
+    """dpo_bfs / dpo_sssp with the timed kernels; timing: device tensor of at
+    least TIMING_BYTES bytes, filled with the per-workgroup phase rows."""
+    rc = lib().dpo_traverse_timed(0 if kind == "bfs" else 1, ctypes.byref(graph.csr()), int(source),
+                                  ctypes.byref(opts.c()), ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.c_void_p(ws.data_ptr()),
+                                  ctypes.c_size_t(ws.numel() * ws.element_size()),
+                                  _stream_ptr(stream), ctypes.c_void_p(timing.data_ptr()),
+                                  ctypes.c_size_t(timing.numel() * timing.element_size()))
+    if rc != DPO_OK:
+        raise DpoError(rc, "dpo_traverse_timed")
 
 
 def alloc_workspace(graph: DeviceGraph, opts: Options, device="cuda"):

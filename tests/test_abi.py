@@ -117,3 +117,4 @@ def test_batch_argument_errors():
     c.graph_vbase = vb_bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     assert f(ctypes.byref(c), qa, 1, ob, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), big, None,
              None) == dpo.DPO_ERR_ARG
+

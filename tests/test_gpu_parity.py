@@ -142,6 +142,36 @@ def test_bfs_small_child_blocks(s12, cb):
         check_bfs_stats(g, want, opts, st)
 
 
+@pytest.mark.parametrize("T,CB,CF,agg,k", [(16, 64, 4, dpo.DPO_AGG_MULTIBLOCK, 4),
+                                         (64, 128, 1, dpo.DPO_AGG_MULTIBLOCK, 4),
+                                         (0, 256, 2, dpo.DPO_AGG_BLOCK, 1),
+                                         (8, 128, 8, dpo.DPO_AGG_WAVE, 1)])
+def test_gpu_counters_match_the_walked_schedule(s12, T, CB, CF, agg, k):
+    """The kernels' counters against the oracle's step-by-step walk of the
+    transformed schedule (threshold, coarsen, aggregate, binary-search
+    disaggregation, coarsening loop; Sec. III-V) over each BFS level set:
+    serial and child edges, launch records and coarsened child blocks are
+    equal, and the kernels publish at most one grid per group."""
+    g, dg = s12
+    lv, depth = oracle.bfs(g, 0)
+    grp = {dpo.DPO_AGG_WAVE: 64, dpo.DPO_AGG_BLOCK: 256, dpo.DPO_AGG_MULTIBLOCK: 256 * k}[agg]
+    walked = {"edges_serial": 0, "edges_child": 0, "records": 0, "child_blocks": 0}
+    max_grids = 0
+    for L in range(depth):
+        frontier = np.flatnonzero(lv == L)
+        serial, child, grids = oracle.simulate_nested(g.row_ptr, frontier, T, CB, CF, grp)
+        walked["edges_serial"] += len(serial)
+        walked["edges_child"] += len(child)
+        walked["records"] += sum(r for r, _ in grids)
+        walked["child_blocks"] += sum(b for _, b in grids)
+        max_grids += -(-frontier.size // grp) if grids else 0
+    opts = dpo.Options(threshold=T, coarsen=CF, agg=agg, agg_blocks=max(k, 2), child_block=CB)
+    got, st = run_bfs(dg, 0, opts)
+    assert np.array_equal(got, lv)
+    assert {key: st[key] for key in walked} == walked, opts.label()
+    assert 1 <= st["descriptors"] <= max_grids, opts.label()
+
+
 @pytest.fixture(scope="module")
 def s14p():
     """Permuted R-MAT scale 14 with weights: frontiers of ragged size."""

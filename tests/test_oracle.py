@@ -60,15 +60,29 @@ def test_bfs_all_graphs_brute_force(n):
             assert depth == hop[s].max() + 1
 
 
-def test_bfs_all_graphs_n6_sampled():
-    # 2^15 graphs on 6 vertices: every 7th graph, all sources
-    for i, edges in enumerate(all_graphs(6)):
-        if i % 7:
-            continue
-        g = gg.from_edges(6, edges)
-        hop = hop_matrix(6, edges)
-        for s in range(6):
-            assert np.array_equal(oracle.bfs(g, s)[0], hop[s])
+def test_bfs_all_graphs_n6():
+    """Every one of the 2^15 labelled simple graphs on 6 vertices, every
+    source: hop distances from boolean matrix powers, computed for all graphs
+    at once (stacked 6 x 6 adjacency matrices)."""
+    n = 6
+    pairs = list(itertools.combinations(range(n), 2))
+    masks = np.arange(1 << len(pairs))
+    adj = np.zeros((masks.size, n, n), dtype=np.int64)
+    for i, (u, v) in enumerate(pairs):
+        bit = (masks >> i) & 1
+        adj[:, u, v] = bit
+        adj[:, v, u] = bit
+    hop = np.full((masks.size, n, n), -1, dtype=np.int64)
+    reach = np.broadcast_to(np.eye(n, dtype=np.int64), adj.shape).copy()
+    hop[reach > 0] = 0
+    for k in range(1, n):
+        reach = ((reach @ adj) > 0).astype(np.int64)
+        hop[(hop == -1) & (reach > 0)] = k
+    for mask in masks:
+        edges = [p for i, p in enumerate(pairs) if mask >> i & 1]
+        g = gg.from_edges(n, edges)
+        for s in range(n):
+            assert np.array_equal(oracle.bfs(g, s)[0], hop[mask, s]), (edges, s)
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -256,14 +270,18 @@ def test_simulated_schedule_covers_each_edge_once(T, CB, CF, grp):
     s = int(gg.sample_sources(g, 1, 3)[0])
     lv, depth = oracle.bfs(g, s)
     rp = g.row_ptr
-    tot = {"serial": 0, "child": 0}
+    tot = {"serial": 0, "child": 0, "records": 0, "blocks": 0}
     for L in range(depth):
         frontier = np.flatnonzero(lv == L)
-        serial, child = oracle.simulate_nested(rp, frontier, T, CB, CF, grp)
+        serial, child, grids = oracle.simulate_nested(rp, frontier, T, CB, CF, grp)
         got = sorted(serial + child)
         want = sorted((int(u), e) for u in frontier for e in range(rp[u], rp[u + 1]))
         assert got == want
+        assert len(grids) <= -(-frontier.size // grp)  # at most one grid per group
         tot["serial"] += len(serial)
         tot["child"] += len(child)
+        tot["records"] += sum(r for r, _ in grids)
+        tot["blocks"] += sum(b for _, b in grids)
     c = oracle.schedule_counts(g, lv, T, CB, CF)
     assert c["edges_serial"] == tot["serial"] and c["edges_child"] == tot["child"]
+    assert c["records"] == tot["records"] and c["child_blocks"] == tot["blocks"]
