@@ -19,8 +19,9 @@
  *
  * Conventions for every call below
  *   - Graph arrays, outputs and the workspace are DEVICE pointers owned by the
- *     caller; the library never allocates device memory and never frees the
- *     caller's memory.  `stream` is a hipStream_t (NULL = default stream).
+ *     caller; the library never allocates device memory at run time (its one
+ *     static device array serves dpo_bfs_noalloc) and never frees the caller's
+ *     memory.  `stream` is a hipStream_t (NULL = default stream).
  *   - The CSR graph must be symmetric for the results to be shortest paths of
  *     an undirected graph; the kernels follow out-edges only.
  *   - Work is enqueued on `stream`.  The traversal calls synchronise `stream`
@@ -153,6 +154,28 @@ dpo_status dpo_bfs(const dpo_csr* g, int32_t source, const dpo_options* o, int32
  * 0xFFFFFFFF or more).  Other arguments as for dpo_bfs. */
 dpo_status dpo_sssp(const dpo_csr* g, int32_t source, const dpo_options* o, uint32_t* dist,
                     void* ws, size_t ws_bytes, void* stream, dpo_stats* st);
+
+/* ------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory: code that must not call
+ * hipMalloc (tight serving loops, harnesses that forbid it) or that cannot
+ * hand the library a workspace.  dpo_bfs_noalloc is dpo_bfs with its
+ * workspace taken from a static device array of DPO_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every GPU it runs on until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree, pinned host memory or HIP
+ * graph instantiation: its level steps are plain kernel launches).
+ *   - Graphs whose dpo_workspace_bytes(g, o) exceed DPO_NOALLOC_SCRATCH_BYTES
+ *     are rejected with DPO_ERR_WORKSPACE before anything is enqueued (up to
+ *     about 925,000 vertices at the default options, 757,000 with
+ *     DPO_AGG_NONE; the size grows with n only).
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents; each call clears what it reads before reading it.
+ *     Calls that overlap in time on one GPU (other threads, other streams)
+ *     race on the array and give undefined results: serialise them.
+ *   - Same arguments, results and errors as dpo_bfs otherwise; no counters. */
+#define DPO_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+dpo_status dpo_bfs_noalloc(const dpo_csr* g, int32_t source, const dpo_options* o, int32_t* levels,
+                           void* stream);
 
 /* ------------------------------------------------------------ phase timing
  * Execution-time breakdown of one traversal (Sec. VIII-B splits time into

@@ -563,6 +563,91 @@ dpo_status traverse_batch(int problem, const dpo_arena* ar, const dpo_query* qs,
 }
 
 
+// ------------------------------------------------------------ no allocation
+// Workspace of dpo_bfs_noalloc: a static device array that every GPU the
+// library runs on holds until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns, kept
+// per device.
+static __device__ __align__(256) unsigned char scratch[DPO_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device (under r.mu)
+
+dpo_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return DPO_ERR_HIP;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DPO_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DPO_OK;
+}
+
+// One level step launched kernel by kernel (no HIP graph: instantiating one
+// allocates).
+dpo_status launch_step(SetRun& sr, uint32_t step) {
+  void* p[] = {&sr.a, &step};
+  if (hipLaunchKernel(sr.parent, dim3((unsigned)sr.pgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
+    return DPO_ERR_HIP;
+  if (sr.child &&
+      hipLaunchKernel(sr.child, dim3((unsigned)sr.cgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
+    return DPO_ERR_HIP;
+  if (sr.serial &&
+      hipLaunchKernel(sr.serial, dim3((unsigned)sr.pgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
+    return DPO_ERR_HIP;
+  return DPO_OK;
+}
+
+dpo_status traverse_noalloc(int problem, const dpo_csr* g, int32_t source, const dpo_options* o,
+                            void* out, void* stream) {
+  if (!o || !out) return DPO_ERR_ARG;
+  dpo_status s = check_graph(g, problem == PROB_SSSP);
+  if (s != DPO_OK) return s;
+  if ((s = check_options(*o)) != DPO_OK) return s;
+  if (source < 0 || source >= g->n) return DPO_ERR_SOURCE;
+  // the static workspace bounds the graph size (checked before any HIP call)
+  if (layout_for(round32(g->n), 1, *o).total > (size_t)DPO_NOALLOC_SCRATCH_BYTES)
+    return DPO_ERR_WORKSPACE;
+  Runtime& r = rt();
+  std::lock_guard<std::mutex> lock(r.mu);
+  if ((s = ensure_device(r)) != DPO_OK) return s;
+  void* ws = nullptr;
+  if ((s = scratch_of_current_device(&ws)) != DPO_OK) return s;
+  SetRun sr;
+  s = prepare_set(r, problem, g, *o, round32(g->n), 1, out, ws, DPO_NOALLOC_SCRATCH_BYTES, stream,
+                  false, &sr);
+  if (s != DPO_OK) return s;
+  // the query record, its index and the admit prefix, from host stack memory
+  // (copied by the runtime before hipMemcpyAsync returns)
+  Query hq[1] = {Query{0, g->n, 0, 0, o->threshold, o->coarsen, 0, source}};
+  int32_t hl[3] = {0, 0, 0};
+  // init_kernel clears the state, the level sets, the group counters and the
+  // statistics rows, and the admit kernels the outputs and visited state, so
+  // nothing left in the array by an earlier call is read
+  if ((s = start_set(r, sr)) != DPO_OK) return s;
+  if ((s = admit(r, sr, hq, hl, 1, 0)) != DPO_OK) return s;
+  uint32_t flags[4] = {0, 0, 0, 0};  // base, done, error, levels_run
+  const int64_t max_replays = (int64_t)g->n / sr.steps + 2;
+  State* st = sr.a.st;
+  uint32_t k = (uint32_t)sr.steps;
+  for (int64_t rep = 0; rep < max_replays; ++rep) {
+    for (int i = 0; i < sr.steps; ++i)
+      if ((s = launch_step(sr, (uint32_t)i)) != DPO_OK) return s;
+    void* ap[] = {&st, &k};
+    if (hipLaunchKernel(advance_kernel_ptr(), dim3(1), dim3(64), ap, 0, sr.stream) != hipSuccess)
+      return DPO_ERR_HIP;
+    if (hipMemcpyAsync(flags, st, sizeof(flags), hipMemcpyDeviceToHost, sr.stream) != hipSuccess ||
+        hipStreamSynchronize(sr.stream) != hipSuccess)
+      return DPO_ERR_HIP;
+    if (flags[2] != 0) return (dpo_status)(-(int32_t)flags[2]);
+    if (flags[1]) return DPO_OK;
+  }
+  return DPO_ERR_TIMEOUT;
+}
+
 // ------------------------------------------------------------ serving engine
 // Continuous batching: queries are admitted at replay boundaries while
 // others are running, as long as their output slots (footprint) and a query
@@ -894,6 +979,11 @@ dpo_status dpo_bfs(const dpo_csr* g, int32_t source, const dpo_options* o, int32
 dpo_status dpo_sssp(const dpo_csr* g, int32_t source, const dpo_options* o, uint32_t* dist,
                     void* ws, size_t ws_bytes, void* stream, dpo_stats* st) {
   return dpo::traverse(dpo::PROB_SSSP, g, source, o, dist, ws, ws_bytes, stream, st);
+}
+
+dpo_status dpo_bfs_noalloc(const dpo_csr* g, int32_t source, const dpo_options* o, int32_t* levels,
+                           void* stream) {
+  return dpo::traverse_noalloc(dpo::PROB_BFS, g, source, o, levels, stream);
 }
 
 dpo_status dpo_traverse_timed(int32_t kind, const dpo_csr* g, int32_t source, const dpo_options* o,

@@ -134,6 +134,9 @@ def lib():
         f.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.POINTER(_Options),
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                       ctypes.POINTER(_Stats)]
+    L.dpo_bfs_noalloc.restype = ctypes.c_int32
+    L.dpo_bfs_noalloc.argtypes = [ctypes.POINTER(_Csr), ctypes.c_int32, ctypes.POINTER(_Options),
+                                  ctypes.c_void_p, ctypes.c_void_p]
     L.dpo_traverse_timed.restype = ctypes.c_int32
     L.dpo_traverse_timed.argtypes = [ctypes.c_int32, ctypes.POINTER(_Csr), ctypes.c_int32,
                                      ctypes.POINTER(_Options), ctypes.c_void_p, ctypes.c_void_p,
@@ -248,6 +251,18 @@ def dpo_sssp(graph: DeviceGraph, source: int, opts: Options, dist, ws, stream=No
              stats: bool = False):
     """dist: int32/uint32 device tensor [n] (written as uint32)."""
     return _traverse(lib().dpo_sssp, "dpo_sssp", graph, source, opts, dist, ws, stream, stats)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DPO_NOALLOC_SCRATCH_BYTES
+
+
+def dpo_bfs_noalloc(graph: DeviceGraph, source: int, opts: Options, levels, stream=None):
+    """dpo_bfs with the library's static device workspace (no allocation; for
+    graphs whose workspace fits NOALLOC_SCRATCH_BYTES)."""
+    rc = lib().dpo_bfs_noalloc(ctypes.byref(graph.csr()), int(source), ctypes.byref(opts.c()),
+                               ctypes.c_void_p(levels.data_ptr()), _stream_ptr(stream))
+    if rc != DPO_OK:
+        raise DpoError(rc, "dpo_bfs_noalloc")
 
 
 TIMING_BYTES = 64 * 3 * 4096 * 8 * 8  # DPO_TIMING_BYTES

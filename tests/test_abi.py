@@ -118,3 +118,23 @@ def test_batch_argument_errors():
     assert f(ctypes.byref(c), qa, 1, ob, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), big, None,
              None) == dpo.DPO_ERR_ARG
 
+
+def test_noalloc_rejects_before_any_device_work():
+    """The no-allocation entry point checks its arguments and the static
+    workspace bound on the host: a graph whose workspace exceeds the static
+    array is refused with DPO_ERR_WORKSPACE, as are bad sources and options."""
+    f = dpo.lib().dpo_bfs_noalloc
+    o = dpo.Options()
+
+    def call(n, m, src, opts=o, levels=1):
+        csr = dpo._Csr(n, m, 8, 8 if m else None, None)
+        return f(ctypes.byref(csr), src, ctypes.byref(opts.c()), ctypes.c_void_p(levels), None)
+
+    assert call(1_000_000, 10, 0) == dpo.DPO_ERR_WORKSPACE
+    assert call(800_000, 10, 0, dpo.Options.naive()) == dpo.DPO_ERR_WORKSPACE
+    assert call(1000, 10, 1000) == dpo.DPO_ERR_SOURCE
+    assert call(1000, 10, 0, dpo.Options(child_block=100)) == dpo.DPO_ERR_ARG
+    assert call(1000, 10, 0, levels=0) == dpo.DPO_ERR_ARG
+    # the bound is the ordinary workspace size
+    assert dpo.dpo_workspace_bytes(_G(900_000, 1), o) <= dpo.NOALLOC_SCRATCH_BYTES
+    assert dpo.dpo_workspace_bytes(_G(1_000_000, 1), o) > dpo.NOALLOC_SCRATCH_BYTES
