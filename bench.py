@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--split-min", type=int, default=None,
                    help="frontier size from which a level uses two visited copies")
     p.add_argument("--agg", default=None, help="none|wave|block|<k>-block")
+    p.add_argument("--serial-wave", type=int, default=None, choices=[0, 1])
+    p.add_argument("--dyn-share", type=int, default=None,
+                   help="percent of the child blocks claimed in chunks (0 = even split)")
     p.add_argument("--breakdown", action="store_true",
                    help="execution-time breakdown (Sec. VIII-B) of bfs22 or sssp21 at CF 1..8")
     p.add_argument("--sweep", action="store_true",
@@ -95,10 +98,11 @@ TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=512, coarsen=1, agg=3, agg_blocks=4, split_min=262144,
-                        child_block=128)}
+                        child_block=128, dyn_share=50)}
 
 
 SERVE_T = {"bfs": 64, "sssp": 256}  # thresholds of the serving engines
+SERVE_DYN = {"bfs": 0, "sssp": 50}  # percent of child blocks claimed in chunks
 
 
 class Workload:
@@ -325,6 +329,8 @@ def calib_lib():
         L.dpo_calib_stream_probe.argtypes = [vp, u32, vp, u32, i32, vp, vp]
         L.dpo_calib_random_atomic_or.argtypes = [vp, u32, u32, i32, vp]
         L.dpo_calib_workgroup_atomics.argtypes = [vp, u32, u32, i32, vp]
+        L.dpo_calib_workgroup_placement.argtypes = [i32, i32, vp, vp]
+        L.dpo_calib_random_coherent_loads.argtypes = [vp, u32, u32, i32, vp, vp]
         _calib = L
     return _calib
 
@@ -364,6 +370,12 @@ def calibrate_primitives(torch):
     res = {}
     for kb in (512, 8 << 10, 16 << 10, 256 << 10):
         res[f"random_load_{kb}KiB_G_per_s"] = round(random_load_rate(torch, kb << 10) / 1e9, 1)
+    for kb in (512, 8 << 10):
+        words = (kb << 10) // 4
+        t = torch.ones(words, dtype=torch.int32, device="cuda")
+        ms = _timed(torch, lambda st: L.dpo_calib_random_coherent_loads(t.data_ptr(), words, 32, grid,
+                                                                        out.data_ptr(), st))
+        res[f"random_coherent_load_{kb}KiB_G_per_s"] = round(grid * 256 * 32 * 8 / (ms * 1e-3) / 1e9, 1)
     n = 128 << 20  # 512 MiB of int32
     a = torch.ones(n, dtype=torch.int32, device="cuda")
     ms = _timed(torch, lambda st: L.dpo_calib_stream(a.data_ptr(), n, 0, grid, out.data_ptr(), st))
@@ -381,6 +393,17 @@ def calibrate_primitives(torch):
         t = torch.zeros(words, dtype=torch.int32, device="cuda")
         ms = _timed(torch, lambda st: L.dpo_calib_random_atomic_or(t.data_ptr(), words, 8, grid, st))
         res[f"random_atomic_or_{kb}KiB_G_per_s"] = round(grid * 256 * 8 * 8 / (ms * 1e-3) / 1e9, 2)
+    # where workgroups run: the XCC id each one reads from its hardware
+    # register, against workgroup % 8 (round-robin placement over the XCDs)
+    for g in (2048, 4096):
+        pl = torch.zeros(2 * g, dtype=torch.int32, device="cuda")
+        if L.dpo_calib_workgroup_placement(g, 256, pl.data_ptr(),
+                                           torch.cuda.current_stream().cuda_stream) != 0:
+            raise RuntimeError("placement probe failed")
+        torch.cuda.synchronize()
+        xcc = pl.cpu().numpy()[0::2] & 0xF
+        res[f"placement_{g}_wg_xcc_equals_wg_mod_8"] = round(float(np.mean(xcc == np.arange(g) % 8)), 4)
+        res[f"placement_{g}_wg_per_xcc"] = np.bincount(xcc, minlength=8).tolist()
     ctr = torch.zeros(8 * 32, dtype=torch.int32, device="cuda")
     for naddr in (1, 8):
         ms = _timed(torch, lambda st: L.dpo_calib_workgroup_atomics(ctr.data_ptr(), naddr, 16, grid, st))
@@ -548,6 +571,10 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
         tuned["coarsen"] = args.coarsen
     if overrides and args.split_min is not None:
         tuned["split_min"] = args.split_min
+    if overrides and args.serial_wave is not None:
+        tuned["serial_wave"] = args.serial_wave
+    if overrides and args.dyn_share is not None:
+        tuned["dyn_share"] = args.dyn_share
     a = agg_of(args.agg) if overrides else None
     if a:
         tuned["agg"], tuned["agg_blocks"] = a
@@ -774,7 +801,9 @@ def bench_batch(args, dpo, torch, full_line=False):
     qs = [(g, s, bucket[g]) for g, s in queries]
     tot, slot0 = dpo.dpo_batch_slots(da, qs)
     out = torch.empty(tot, dtype=torch.int32, device="cuda")
-    ws = torch.empty(dpo.dpo_batch_workspace_bytes(da, qs, tuned[0]), dtype=torch.uint8,
+    # one workspace for the tuned and the untuned point (granularities differ)
+    ws = torch.empty(max(dpo.dpo_batch_workspace_bytes(da, qs, tuned[0]),
+                         dpo.dpo_batch_workspace_bytes(da, qs, base)), dtype=torch.uint8,
                      device="cuda")
     deg = [g.degrees() for g in graphs]
     st = dpo.dpo_bfs_batch(da, qs, tuned, out, ws, stats=True)
@@ -934,7 +963,8 @@ def bench_serve(args, dpo, torch, full_line=False):
     def opts(kind):
         T = args.threshold if args.threshold is not None else SERVE_T[kind]
         return [dpo.Options(threshold=T, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
-                            steps_per_replay=4, child_block=128)]
+                            steps_per_replay=4, child_block=128,
+                            dyn_share=SERVE_DYN[kind])]
     s_bfs, s_sssp = torch.cuda.Stream(), torch.cuda.Stream()
     max_slots = 1 << 24
     engines = {"bfs": dpo.Engine(da, "bfs", opts("bfs"), max_queries=256, max_slots=max_slots,
@@ -1090,6 +1120,29 @@ def phase_split(rows, mhz=REALTIME_MHZ):
     return tot, per_level, (imb_num / imb_den if imb_den else 1.0)
 
 
+def child_skew(rows, mhz=REALTIME_MHZ):
+    """Where the child kernel's imbalance comes from, time-weighted over the
+    levels: spread of workgroup entries and exits (us) and the ratio of the
+    slowest to the fastest XCD's mean workgroup span (workgroup % 8)."""
+    acc = {"start_spread_us": 0.0, "end_spread_us": 0.0, "xcd_span_ratio": 0.0}
+    wsum = 0.0
+    for L in range(rows.shape[0]):
+        r = rows[L, 1]
+        idx = np.flatnonzero(r[:, 1] != 0)
+        if idx.size < 8:
+            continue
+        r = r[idx]
+        t0, t1 = r[:, 0].astype(np.float64), r[:, 1].astype(np.float64)
+        span = (t1.max() - t0.min()) / mhz
+        wg = (t1 - t0) / mhz
+        per = [wg[idx % 8 == x].mean() for x in range(8) if np.any(idx % 8 == x)]
+        acc["start_spread_us"] += span * (t0.max() - t0.min()) / mhz
+        acc["end_spread_us"] += span * (t1.max() - t1.min()) / mhz
+        acc["xcd_span_ratio"] += span * max(per) / max(min(per), 1e-9)
+        wsum += span
+    return {k: round(v / wsum, 3) if wsum else None for k, v in acc.items()}
+
+
 def bench_breakdown(args, dpo, torch):
     """Sec. VIII-B: parent / aggregation / launch / disaggregation / child time
     per traversal at CF 1, 2, 4, 8 and a few thresholds, from the timed
@@ -1112,7 +1165,7 @@ def bench_breakdown(args, dpo, torch):
             pc, _ = measure(dpo, torch, wl, dg, o, 2, 1)
             ws = dpo.alloc_workspace(dg, o)
             acc = dict.fromkeys(phases, 0.0)
-            longest, imb, timed_ms = None, [], []
+            longest, imb, timed_ms, skews = None, [], [], []
             for s in wl.sources:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
@@ -1122,6 +1175,8 @@ def bench_breakdown(args, dpo, torch):
                 timed_ms.append(e0.elapsed_time(e1))
                 rows = timing.cpu().numpy().view(np.uint64).reshape(64, 3, 4096, 8)
                 tot, per_level, ib = phase_split(rows)
+                skews.append(child_skew(rows))
+                grids = [int((rows[:, k, :, 1] != 0).sum(axis=1).max()) for k in range(3)]
                 for p in phases:
                     acc[p] += tot[p] / len(wl.sources)
                 imb.append(ib)
@@ -1133,6 +1188,9 @@ def bench_breakdown(args, dpo, torch):
                  "timed_ms_per_traversal": round(float(np.mean(timed_ms)), 4),
                  "us_per_traversal": {p: round(v, 1) for p, v in acc.items()},
                  "child_imbalance": round(float(np.mean(imb)), 3),
+                 "workgroups_with_rows": grids,
+                 "child_skew": {k: round(float(np.mean([x[k] for x in skews if x[k] is not None])), 3)
+                                for k in skews[0]},
                  "longest_level": {"level": longest[0],
                                    "us": {p: round(v, 1) for p, v in longest[1].items()}}}
             results.append(r)
@@ -1145,7 +1203,9 @@ def bench_breakdown(args, dpo, torch):
           f"aggregation, {steps} level steps per replay, {len(wl.sources)} source(s).", "",
           f"Command (MI355X, repository root): `{cmd}`", "",
           "Method: the timed instantiations of the level kernels (dpo_traverse_timed: the same "
-          "kernels and grids as the product ones, with a shader-clock stamp at each phase "
+          "kernels as the product ones on the same grids (or, where a timed kernel needs more "
+          "registers, the grid resident at its own occupancy: see the workgroup counts below), "
+          "with a shader-clock stamp at each phase "
           "boundary after the wave's outstanding memory operations) give each workgroup's "
           "cycles per phase and its entry / exit on a 100 MHz clock.  Each kernel's span is "
           "split among the phases in proportion to the cycles; the gap from the parent "
@@ -1168,7 +1228,15 @@ def bench_breakdown(args, dpo, torch):
                   f"{r['timed_ms_per_traversal']:.3f} | " +
                   " | ".join(f"{u[p]:.1f}" for p in phases) + f" | {r['child_imbalance']:.2f} |")
     md += ["", "child imbalance: time-weighted ratio of the busiest child workgroup's span to the "
-           "mean workgroup span.", "", "## Longest level of any source (us)", "",
+           "mean workgroup span.", "", "## Child kernel skew (time-weighted over levels)", "",
+           "| T | CF | entry spread us | exit spread us | slowest / fastest XCD mean span |",
+           "|---|---|---|---|---|"]
+    md += [f"| {r['threshold']} | {r['coarsen']} | {r['child_skew']['start_spread_us']} | "
+           f"{r['child_skew']['end_spread_us']} | {r['child_skew']['xcd_span_ratio']} |" for r in results]
+    md += ["", "Workgroups that stamped rows (largest level; parent, child, thresholded-children "
+           "kernel): " + "; ".join(f"T{r['threshold']} CF{r['coarsen']}: {r['workgroups_with_rows']}"
+                                   for r in results[:3]) + "."]
+    md += ["", "## Longest level of any source (us)", "",
            "| T | CF | level | parent | aggregation | launch | disaggregation | child | gaps |",
            "|---|---|---|---|---|---|---|---|---|"]
     for r in results:

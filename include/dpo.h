@@ -97,6 +97,16 @@ typedef struct {
                                busy); 0: each runs sequentially in its parent's
                                lane, the paper's literal form.  The flat mode
                                always uses the literal form.  Speed only.        */
+  int32_t dyn_share;        /* 0..100, default 0.  How the child kernel's waves
+                               share a level's aggregated child blocks.  0: each
+                               wave runs an even share.  Otherwise each XCD's
+                               workgroups (workgroup % 8) take that XCD's eighth
+                               of the blocks, each wave an even share of
+                               (100 - dyn_share)% of it, and then claim chunks of
+                               the rest from a counter of their XCD until none is
+                               left (as a hardware block scheduler hands out
+                               blocks), so waves whose blocks run slow do fewer.
+                               Speed only.                                      */
 } dpo_options;
 
 typedef struct {
@@ -181,7 +191,9 @@ dpo_status dpo_bfs_noalloc(const dpo_csr* g, int32_t source, const dpo_options* 
  * Execution-time breakdown of one traversal (Sec. VIII-B splits time into
  * parent work, aggregation, launch, disaggregation and child work).  Runs
  * dpo_bfs (kind 0) or dpo_sssp (kind 1) with timed instantiations of the
- * level kernels, on the same grids, so with the same schedule and results.
+ * level kernels, with the same results, on the product kernels' grids (a
+ * timed kernel that needs more registers, and so fits fewer workgroups per
+ * compute unit, runs on the grid resident at its own occupancy).
  * Each wave stamps a shader-clock counter at phase boundaries, after waiting
  * for its own outstanding memory operations (so the timed traversal is
  * slower than the product one), and each workgroup of each level kernel

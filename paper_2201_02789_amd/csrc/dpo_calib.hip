@@ -46,6 +46,27 @@ __global__ __launch_bounds__(256) void random_loads(const uint32_t* __restrict__
   out[tid] = acc;
 }
 
+// The same with agent-scope (device-coherent) loads, as the kernels' checks of
+// a copy that other workgroups update during a level.
+__global__ __launch_bounds__(256) void random_coherent_loads(const uint32_t* __restrict__ table,
+                                                             uint32_t mask, uint32_t iters,
+                                                             uint32_t* __restrict__ out) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t x = tid * 0x9E3779B9u + 0x7F4A7C15u;
+  uint32_t acc = 0;
+  for (uint32_t i = 0; i < iters; ++i) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x = xorshift(x);
+      v[u] = __hip_atomic_load(&table[x & mask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  out[tid] = acc;
+}
+
 // Grid-stride sum of n int32 elements, 8 per lane per step.
 __global__ __launch_bounds__(256) void stream_int(const int32_t* __restrict__ a, uint32_t n,
                                                   uint32_t* __restrict__ out) {
@@ -131,9 +152,28 @@ __global__ __launch_bounds__(64) void workgroup_atomics(uint32_t* __restrict__ c
   for (uint32_t i = 0; i < iters; ++i) atomicAdd(c, 1u);
 }
 
+// The XCC (XCD) each workgroup runs on, from the hardware register, and the
+// compute unit: out[2 * w] = XCC id, out[2 * w + 1] = HW_ID bits.
+__global__ void workgroup_placement(uint32_t* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  uint32_t xcc, hw;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
+  out[2 * blockIdx.x] = xcc;
+  out[2 * blockIdx.x + 1] = hw;
+}
+
 }  // namespace
 
 extern "C" {
+
+// out: device uint32[2 * grid].
+int dpo_calib_workgroup_placement(int grid, int block, uint32_t* out, void* stream) {
+  if (!out || grid < 1 || block < 1 || block > 1024) return -1;
+  hipLaunchKernelGGL(workgroup_placement, dim3(grid), dim3(block), 0, (hipStream_t)stream, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 
 // Each entry point launches one kernel on `stream` and returns 0, or -1 when
 // the launch fails or an argument is outside what the kernel assumes.
@@ -142,6 +182,14 @@ int dpo_calib_random_loads(const uint32_t* table, uint32_t table_words, uint32_t
                            uint32_t* out, void* stream) {
   if (!table || !out || grid < 1 || table_words == 0 || (table_words & (table_words - 1))) return -1;
   hipLaunchKernelGGL(random_loads, dim3(grid), dim3(256), 0, (hipStream_t)stream, table,
+                     table_words - 1, iters, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int dpo_calib_random_coherent_loads(const uint32_t* table, uint32_t table_words, uint32_t iters,
+                                    int grid, uint32_t* out, void* stream) {
+  if (!table || !out || grid < 1 || table_words == 0 || (table_words & (table_words - 1))) return -1;
+  hipLaunchKernelGGL(random_coherent_loads, dim3(grid), dim3(256), 0, (hipStream_t)stream, table,
                      table_words - 1, iters, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

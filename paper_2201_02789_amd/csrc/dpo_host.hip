@@ -105,6 +105,7 @@ dpo_status check_options(const dpo_options& o) {
   if (o.agg_threshold < 0) return DPO_ERR_ARG;
   if (o.split_min < 0) return DPO_ERR_ARG;
   if (o.serial_wave != 0 && o.serial_wave != 1) return DPO_ERR_ARG;
+  if (o.dyn_share < 0 || o.dyn_share > 100) return DPO_ERR_ARG;
   if (o.agg == DPO_AGG_MULTIBLOCK && (o.agg_blocks < 2 || o.agg_blocks > 1024)) return DPO_ERR_ARG;
   if (o.child_block != 64 && o.child_block != 128 && o.child_block != 256) return DPO_ERR_ARG;
   if (o.steps_per_replay < 0 || o.steps_per_replay > 1024) return DPO_ERR_ARG;
@@ -332,6 +333,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.agg_threshold = o.agg_threshold;
   a.split_min = o.split_min;
   a.serial_wave = o.serial_wave;
+  a.dyn_pct = o.dyn_share;
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
@@ -348,6 +350,12 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
     sr->parent = parent_kernel_ptr(problem, gran, true);
     sr->child = sr->child ? child_kernel_ptr(problem, true) : nullptr;
     sr->serial = serial_kernel_ptr(problem, gran, true);
+    // a timed kernel that needs more registers than its product one runs on
+    // the grid that is resident at its own occupancy (a larger grid would run
+    // in two rounds and time the second round's wait as work)
+    sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->parent));
+    if (sr->serial) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->serial));
+    if (sr->child) sr->cgrid = std::min(sr->cgrid, persistent_grid(r, sr->child));
     a.tm = tm;
   }
   return DPO_OK;
@@ -937,6 +945,7 @@ void dpo_default_options(dpo_options* o) {
   o->agg_threshold = 0;
   o->split_min = 65536;
   o->serial_wave = 1;
+  o->dyn_share = 0;
 }
 
 size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o) {

@@ -49,6 +49,8 @@ struct LevelSet {
                                        // buffer, bit 1 split (claims in the other one)
   uint32_t pad0[14];
   unsigned long long qctr[NQD];        // descriptor queues: hi32 count, lo32 child blocks
+  uint32_t cclaim[NQD][32];            // child kernel: chunks claimed per XCD group (one
+                                       // 128-byte line each)
 };
 
 struct State {
@@ -117,7 +119,8 @@ struct Args {
                                    // visited copy and updates the other
   int32_t serial_wave;             // thresholded children: run by the wave together
                                    // (1) or each in its parent's lane (0)
-  int32_t pad2;
+  int32_t dyn_pct;                 // child kernel: percent of each XCD group's blocks
+                                   // that its waves claim in chunks (0 = even split)
 };
 
 // timed: the instantiation that stamps its phases into Args::tm

@@ -519,6 +519,7 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     LevelSet* z = &st->set[(L + 1) % 3];  // idle until level L + 1
     if (tid <= NQF) z->fcnt[tid] = 0;
     if (tid < NQD) z->qctr[tid] = 0;
+    if (tid < NQD) z->cclaim[tid][0] = 0;
     if (tid == 0) {
       st->levels_run = L + 1;
       cur->vmode = vc | (split ? 2u : 0u);  // for this level's child kernel
@@ -1075,104 +1076,139 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   if (B == 0) return;
   const uint32_t vm = cur->vmode;
   const Vis vis = vis_of<P>(a, vm & 1u, (vm & 2u) != 0);
-  const uint32_t nwaves = gridDim.x * NW, gw = blockIdx.x * NW + wave;
-  const uint32_t t0 = (uint32_t)((uint64_t)gw * B / nwaves);
-  const uint32_t t1 = (uint32_t)((uint64_t)(gw + 1) * B / nwaves);
+  // Blocks of the level for this wave.  dyn_pct = 0: an even share of all B.
+  // Otherwise the blocks are split into one range per XCD group (workgroups w
+  // with the same w % 8, which run on the same XCD); a wave takes an even
+  // share of (100 - dyn_pct)% of its group's range, then claims chunks of the
+  // rest from its group's counter until none is left, as a hardware block
+  // scheduler hands out the blocks of a grid.
+  uint32_t t0, t1, dyn0 = 0, dyn1 = 0, csz = 1, xg = 0;
+  if (a.dyn_pct == 0 || gridDim.x % NQD) {
+    const uint32_t nwaves = gridDim.x * NW, gw = blockIdx.x * NW + wave;
+    t0 = (uint32_t)((uint64_t)gw * B / nwaves);
+    t1 = (uint32_t)((uint64_t)(gw + 1) * B / nwaves);
+  } else {
+    xg = blockIdx.x % NQD;
+    const uint32_t nwx = (gridDim.x / NQD) * NW, k = (blockIdx.x / NQD) * NW + wave;
+    const uint32_t r0 = (uint32_t)((uint64_t)xg * B / NQD);
+    const uint32_t r1 = (uint32_t)((uint64_t)(xg + 1) * B / NQD);
+    const uint32_t share = (uint32_t)((uint64_t)(r1 - r0) * (uint32_t)(100 - a.dyn_pct) / 100u) / nwx;
+    t0 = r0 + k * share;
+    t1 = t0 + share;
+    dyn0 = r0 + nwx * share;
+    dyn1 = r1;
+    csz = max(1u, (dyn1 - dyn0) / (2u * nwx));  // about two chunks per wave
+  }
   Counters cn{0, 0, 0, 0, 0, 0, 0};
   Stage s{s_stage[wave], 0u};
   pc.mark(TP_LAUNCH);  // reading the level's published grids
 
-  if (t0 < t1) {
-    // disaggregation of the first block (Sec. V-A): queue, descriptor, record
-    uint32_t q = 0;
-    while (t0 >= s_qpre[q + 1]) ++q;
-    const int4* dq = a.desc + (size_t)q * a.desc_cap;
-    const uint32_t tq = t0 - s_qpre[q];
-    uint32_t d = wave_upper_search(s_qnd[q], tq, lane, [&](uint32_t p) { return (uint32_t)dq[p].z; });
-    int4 dd = dq[d];
-    uint32_t r = wave_upper_search((uint32_t)dd.y, tq - (uint32_t)dd.z, lane,
-                                   [&](uint32_t p) { return (uint32_t)a.rec[dd.x + p].z; });
-    constexpr int U = 8;
-    while (true) {
-      const uint32_t wn = min(64u, (uint32_t)dd.y - r);
-      const Window win = load_window<P>(a, vis.claim, (uint32_t)dd.x + r, wn,
-                                        s_qpre[q] + (uint32_t)dd.z, t0, t1, lane, L, cn.child);
-      pc.mark(TP_DISAGG);
-      if (win.bad) {
-        if (lane == 0) set_error(st, ERR_CAPACITY);
-        break;
-      }
-      // Coarsening loop (Sec. IV-B): a coarsened block covers original blocks
-      // j*CF .. j*CF+CF-1 of CB lanes, the contiguous edges [j*CF*CB,
-      // (j+1)*CF*CB) of its row, taken here 64 lanes at a time.
-      // SSSP: the parents' distances are loaded again with each batch and
-      // checked at the next one (by then the load has returned), so shares of
-      // parents lowered while the wave runs them are cut short.
-      uint32_t pnow = 0xFFFFFFFFu;
-      for (uint32_t x0 = 0; x0 < win.nslices; x0 += U) {
-        int32_t v[U], out[U];
-        uint32_t w[U];
-        Elem c[U];
-        unsigned long long sup = 0ull;  // records whose parent was lowered
-        if (P == PROB_SSSP) {
-          sup = __ballot((uint32_t)lane < wn && pnow < win.du);
-          if ((uint32_t)lane < wn) pnow = coherent_load(&vis.claim[win.ps]);
+  bool failed = false;
+  while (true) {
+    if (t0 < t1) {
+      // disaggregation of the first block (Sec. V-A): queue, descriptor, record
+      uint32_t q = 0;
+      while (t0 >= s_qpre[q + 1]) ++q;
+      const int4* dq = a.desc + (size_t)q * a.desc_cap;
+      const uint32_t tq = t0 - s_qpre[q];
+      uint32_t d = wave_upper_search(s_qnd[q], tq, lane, [&](uint32_t p) { return (uint32_t)dq[p].z; });
+      int4 dd = dq[d];
+      uint32_t r = wave_upper_search((uint32_t)dd.y, tq - (uint32_t)dd.z, lane,
+                                     [&](uint32_t p) { return (uint32_t)a.rec[dd.x + p].z; });
+      constexpr int U = 8;
+      while (true) {
+        const uint32_t wn = min(64u, (uint32_t)dd.y - r);
+        const Window win = load_window<P>(a, vis.claim, (uint32_t)dd.x + r, wn,
+                                          s_qpre[q] + (uint32_t)dd.z, t0, t1, lane, L, cn.child);
+        pc.mark(TP_DISAGG);
+        if (win.bad) {
+          if (lane == 0) set_error(st, ERR_CAPACITY);
+          failed = true;
+          break;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          v[u] = -1;
-          w[u] = 0u;
-          c[u] = Elem{0, 0, 0, 0, 0u};
-          const uint32_t x = x0 + u;
-          if (x < win.nslices) {
-            // record of slice x: the last lane whose scan start is <= x
-            const uint32_t k =
-                (uint32_t)__popcll(__ballot((uint32_t)lane < wn && win.excl <= x)) - 1u;
-            const int32_t rs = __builtin_amdgcn_readlane(win.rs, k);
-            const int32_t e0 = rs + __builtin_amdgcn_readlane(win.elo, k) +
-                               (int32_t)((x - (uint32_t)__builtin_amdgcn_readlane((int32_t)win.excl, k)) * 64u);
-            const int32_t e1 = rs + __builtin_amdgcn_readlane(win.ehi, k);
-            c[u].vbase = __builtin_amdgcn_readlane(win.vbase, k);
-            c[u].n = __builtin_amdgcn_readlane(win.n, k);
-            c[u].sbase = __builtin_amdgcn_readlane(win.sbase, k);
-            c[u].lv = __builtin_amdgcn_readlane(win.lv, k);
-            c[u].du = (uint32_t)__builtin_amdgcn_readlane((int32_t)win.du, k);
-            if (e0 + lane < e1 && !((sup >> k) & 1ull)) {
-              v[u] = a.col[e0 + lane];
-              if (P == PROB_SSSP) w[u] = a.w[e0 + lane];
+        // Coarsening loop (Sec. IV-B): a coarsened block covers original blocks
+        // j*CF .. j*CF+CF-1 of CB lanes, the contiguous edges [j*CF*CB,
+        // (j+1)*CF*CB) of its row, taken here 64 lanes at a time.
+        // SSSP: the parents' distances are loaded again with each batch and
+        // checked at the next one (by then the load has returned), so shares of
+        // parents lowered while the wave runs them are cut short.
+        uint32_t pnow = 0xFFFFFFFFu;
+        for (uint32_t x0 = 0; x0 < win.nslices; x0 += U) {
+          int32_t v[U], out[U];
+          uint32_t w[U];
+          Elem c[U];
+          unsigned long long sup = 0ull;  // records whose parent was lowered
+          if (P == PROB_SSSP) {
+            sup = __ballot((uint32_t)lane < wn && pnow < win.du);
+            if ((uint32_t)lane < wn) pnow = coherent_load(&vis.claim[win.ps]);
+          }
+  #pragma unroll
+          for (int u = 0; u < U; ++u) {
+            v[u] = -1;
+            w[u] = 0u;
+            c[u] = Elem{0, 0, 0, 0, 0u};
+            const uint32_t x = x0 + u;
+            if (x < win.nslices) {
+              // record of slice x: the last lane whose scan start is <= x
+              const uint32_t k =
+                  (uint32_t)__popcll(__ballot((uint32_t)lane < wn && win.excl <= x)) - 1u;
+              const int32_t rs = __builtin_amdgcn_readlane(win.rs, k);
+              const int32_t e0 = rs + __builtin_amdgcn_readlane(win.elo, k) +
+                                 (int32_t)((x - (uint32_t)__builtin_amdgcn_readlane((int32_t)win.excl, k)) * 64u);
+              const int32_t e1 = rs + __builtin_amdgcn_readlane(win.ehi, k);
+              c[u].vbase = __builtin_amdgcn_readlane(win.vbase, k);
+              c[u].n = __builtin_amdgcn_readlane(win.n, k);
+              c[u].sbase = __builtin_amdgcn_readlane(win.sbase, k);
+              c[u].lv = __builtin_amdgcn_readlane(win.lv, k);
+              c[u].du = (uint32_t)__builtin_amdgcn_readlane((int32_t)win.du, k);
+              if (e0 + lane < e1 && !((sup >> k) & 1ull)) {
+                v[u] = a.col[e0 + lane];
+                if (P == PROB_SSSP) w[u] = a.w[e0 + lane];
+              }
             }
           }
-        }
-        if (a.count_stats) {  // edges run (lane 0 keeps the wave's count)
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const uint32_t nv = (uint32_t)__popcll(__ballot(v[u] >= 0));
-            if (lane == 0) cn.echild += nv;
+          if (a.count_stats) {  // edges run (lane 0 keeps the wave's count)
+  #pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const uint32_t nv = (uint32_t)__popcll(__ballot(v[u] >= 0));
+              if (lane == 0) cn.echild += nv;
+            }
           }
+          visit_batch<P, U>(a, vis, v, w, c, L, out);
+  #pragma unroll
+          for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
         }
-        visit_batch<P, U>(a, vis, v, w, c, L, out);
-#pragma unroll
-        for (int u = 0; u < U; ++u) stage_push(s, out[u] >= 0, out[u], a, cur, fout, lane);
-      }
-      pc.mark(TP_CHILD);
-      if (win.last) break;
-      // next window: rest of this descriptor, else the next one (next queue
-      // if need be)
-      r += wn;
-      if (r >= (uint32_t)dd.y) {
-        r = 0;
-        if (++d >= s_qnd[q]) {
-          d = 0;
-          do { ++q; } while (q < NQD && s_qnd[q] == 0);
-          if (q >= NQD) {
-            if (lane == 0) set_error(st, ERR_CAPACITY);
-            break;
+        pc.mark(TP_CHILD);
+        if (win.last) break;
+        // next window: rest of this descriptor, else the next one (next queue
+        // if need be)
+        r += wn;
+        if (r >= (uint32_t)dd.y) {
+          r = 0;
+          if (++d >= s_qnd[q]) {
+            d = 0;
+            do { ++q; } while (q < NQD && s_qnd[q] == 0);
+            if (q >= NQD) {
+              if (lane == 0) set_error(st, ERR_CAPACITY);
+              failed = true;
+              break;
+            }
+            dq = a.desc + (size_t)q * a.desc_cap;
           }
-          dq = a.desc + (size_t)q * a.desc_cap;
+          dd = dq[d];
         }
-        dd = dq[d];
       }
     }
+    // next chunk of the group's dynamic part, if any is left
+    if (failed || dyn0 >= dyn1) break;
+    uint32_t j = 0;
+    if (lane == 0) j = atomicAdd(&cur->cclaim[xg][0], 1u);
+    j = __shfl(j, 0, 64);
+    const uint64_t c0 = (uint64_t)dyn0 + (uint64_t)j * csz;
+    if (c0 >= dyn1) break;
+    t0 = (uint32_t)c0;
+    t1 = min(t0 + csz, dyn1);
+    pc.mark(TP_LAUNCH);
   }
   block_flush(s, a, cur, fout, tid, s_bc);
   add_stats(a, s_stats, cn, tid);

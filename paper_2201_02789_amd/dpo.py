@@ -47,7 +47,8 @@ class _Options(ctypes.Structure):
                 ("coarsen", ctypes.c_int32), ("agg", ctypes.c_int32),
                 ("agg_blocks", ctypes.c_int32), ("child_block", ctypes.c_int32),
                 ("steps_per_replay", ctypes.c_int32), ("agg_threshold", ctypes.c_int32),
-                ("split_min", ctypes.c_int32), ("serial_wave", ctypes.c_int32)]
+                ("split_min", ctypes.c_int32), ("serial_wave", ctypes.c_int32),
+                ("dyn_share", ctypes.c_int32)]
 
 
 class _Csr(ctypes.Structure):
@@ -85,6 +86,7 @@ class Options:
     agg_threshold: int = 0
     split_min: int = 65536
     serial_wave: int = 1
+    dyn_share: int = 0
 
     def c(self) -> _Options:
         return _Options(*(int(getattr(self, f.name)) for f in fields(self)))
@@ -108,6 +110,7 @@ class Options:
         at = f"-A{self.agg_threshold}" if self.agg_threshold else ""
         sm = f"-S{self.split_min}" if self.split_min != 65536 else ""
         sl = "-lane" if not self.serial_wave else ""
+        sl += f"-D{self.dyn_share}" if self.dyn_share else ""
         cb = f"-CB{self.child_block}" if self.child_block != 256 else ""
         return f"T{self.threshold}-CF{self.coarsen}-{g}{cb}{at}{sm}{sl}"
 

@@ -85,3 +85,19 @@ def test_phase_split_on_known_rows():
     assert abs(sum(per_level[0][1].values()) - 3.2) < 1e-9  # 0 .. 320 ticks
     # child workgroup spans 200 and 90 ticks: busiest / mean = 200 / 145
     assert abs(imb - 200 / 145) < 1e-9
+
+
+def test_child_skew_on_known_rows():
+    """Sixteen child workgroups, those on XCD 3 (workgroups 3 and 11) twice as
+    long as the others; entries spread over 10 ticks, exits as they fall."""
+    rows = np.zeros((64, 3, 4096, 8), dtype=np.uint64)
+    for w in range(16):
+        t0 = 100 + (w % 11)  # entries 100 .. 110
+        span = 200 if w % 8 == 3 else 100
+        rows[0, 1, w, 0], rows[0, 1, w, 1] = t0, t0 + span
+        rows[0, 1, w, 6] = 1
+    sk = bench.child_skew(rows)
+    assert abs(sk["start_spread_us"] - 0.10) < 1e-9
+    assert abs(sk["xcd_span_ratio"] - 2.0) < 1e-9
+    t1 = [100 + (w % 11) + (200 if w % 8 == 3 else 100) for w in range(16)]
+    assert abs(sk["end_spread_us"] - (max(t1) - min(t1)) / 100) < 1e-9

@@ -213,6 +213,42 @@ def test_visited_copies_every_mode(s14p, split_min):
             assert np.array_equal(got_d, oracle.dijkstra(g, s)), (opts.label(), s)
 
 
+@pytest.mark.parametrize("dyn", [10, 25, 50, 100])
+def test_dynamic_child_shares(s14p, dyn):
+    """Child blocks claimed in chunks per XCD group (dyn_share): every block
+    still runs exactly once, so levels, distances and the BFS counters equal
+    the oracle's, at several thresholds, coarsening factors, granularities and
+    child block sizes, with the workspace reused across sources."""
+    g, dg = s14p
+    srcs = [int(s) for s in gg.sample_sources(g, 2, 8)] + [gg.max_degree_vertex(g)]
+    for opts in (dpo.Options(threshold=64, coarsen=1, child_block=128, dyn_share=dyn),
+                 dpo.Options(threshold=0, coarsen=4, agg=dpo.DPO_AGG_BLOCK, dyn_share=dyn),
+                 dpo.Options.naive(child_block=64, dyn_share=dyn),
+                 dpo.Options(threshold=8, coarsen=2, agg=dpo.DPO_AGG_WAVE, split_min=0, dyn_share=dyn),
+                 dpo.Options(threshold=512, coarsen=1, child_block=128, split_min=262144,
+                             dyn_share=dyn)):
+        ws = dpo.alloc_workspace(dg, opts)
+        for s in srcs:
+            print("dyn", opts.label(), s, flush=True)
+            want = oracle.bfs(g, s)[0]
+            got, st = run_bfs(dg, s, opts, ws=ws)
+            assert np.array_equal(got, want), (opts.label(), s)
+            check_bfs_stats(g, want, opts, st)
+            got_d, st_d = run_sssp(dg, s, opts, ws=ws, stats=True)
+            assert np.array_equal(got_d, oracle.dijkstra(g, s)), (opts.label(), s)
+    # one hub record far larger than a chunk
+    star = gg.add_weights(gg.star_graph(300_001), 5)
+    ds = dpo.DeviceGraph.from_host(star)
+    for s in (0, 17):
+        o = dpo.Options(threshold=32, coarsen=1, child_block=128, dyn_share=dyn)
+        got, st = run_bfs(ds, s, o)
+        want = oracle.bfs(star, s)[0]
+        assert np.array_equal(got, want)
+        check_bfs_stats(star, want, o, st)
+        got_d, _ = run_sssp(ds, s, o)
+        assert np.array_equal(got_d, oracle.dijkstra(star, s))
+
+
 def test_sssp_large_distances():
     """Distances from 0 up to ~10^8 on a 60 x 55 grid give the oracle's
     distances."""

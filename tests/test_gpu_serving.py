@@ -28,12 +28,13 @@ def resident():
 
 
 @pytest.mark.parametrize("kind", ["bfs", "sssp"])
-@pytest.mark.parametrize("agg,steps,split_min", [(dpo.DPO_AGG_MULTIBLOCK, 2, 65536),
-                                                 (dpo.DPO_AGG_BLOCK, 5, 65536),
-                                                 (dpo.DPO_AGG_NONE, 3, 65536),
-                                                 (dpo.DPO_AGG_MULTIBLOCK, 3, 0),
-                                                 (dpo.DPO_AGG_MULTIBLOCK, 2, 300)])
-def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, split_min):
+@pytest.mark.parametrize("agg,steps,split_min,dyn", [(dpo.DPO_AGG_MULTIBLOCK, 2, 65536, 0),
+                                                     (dpo.DPO_AGG_BLOCK, 5, 65536, 0),
+                                                     (dpo.DPO_AGG_NONE, 3, 65536, 0),
+                                                     (dpo.DPO_AGG_MULTIBLOCK, 3, 0, 0),
+                                                     (dpo.DPO_AGG_MULTIBLOCK, 2, 300, 0),
+                                                     (dpo.DPO_AGG_MULTIBLOCK, 3, 65536, 25)])
+def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, split_min, dyn):
     graphs, da = resident
     rng = np.random.default_rng(11)
     reqs = []
@@ -41,9 +42,9 @@ def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, s
         g = int(rng.integers(0, len(graphs)))
         reqs.append((g, int(gg.sample_sources(graphs[g], 1, int(rng.integers(1 << 30)))[0])))
     bopts = [dpo.Options(threshold=16, coarsen=2, agg=agg, steps_per_replay=steps,
-                         split_min=split_min),
+                         split_min=split_min, dyn_share=dyn),
              dpo.Options(threshold=64, coarsen=1, agg=agg, steps_per_replay=steps,
-                         split_min=split_min)]
+                         split_min=split_min, dyn_share=dyn)]
     gb = [0 if g.n < 2048 else 1 for g in graphs]
     # pool of 12k slots: at most a few graphs at once, so admission waits on footprint
     eng = dpo.Engine(da, kind, bopts, graph_bucket=gb, max_queries=8, max_slots=12 * 1024)
@@ -99,7 +100,8 @@ def _serving_opts(which):
         # per kind
         import bench
         return {k: [dpo.Options(threshold=bench.SERVE_T[k], coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK,
-                                agg_blocks=4, steps_per_replay=4, child_block=128)]
+                                agg_blocks=4, steps_per_replay=4, child_block=128,
+                                dyn_share=bench.SERVE_DYN[k])]
                 for k in ("bfs", "sssp")}
     o = [dpo.Options(threshold=32, coarsen=1, steps_per_replay=4)]
     return {"bfs": o, "sssp": o}
