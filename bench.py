@@ -93,7 +93,7 @@ def agg_of(s):
 # blockDim, which the naive baseline shares) is 128 lanes on the large
 # workloads: the child kernel splits a level's blocks evenly over its waves,
 # and smaller blocks make equal block counts closer to equal edge counts.
-TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
+TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128, dyn_share=25),
          "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
@@ -1143,6 +1143,31 @@ def child_skew(rows, mhz=REALTIME_MHZ):
     return {k: round(v / wsum, 3) if wsum else None for k, v in acc.items()}
 
 
+def level_table(rows, mhz=REALTIME_MHZ):
+    """Per level of one timed traversal: each kernel's span (first entry to last
+    exit, us) and, for the child kernel, the mean and the largest workgroup span
+    and the spread of workgroup exits."""
+    out = []
+    for L in range(rows.shape[0]):
+        row = {"level": L}
+        for k, name in ((0, "parent"), (1, "child"), (2, "serial")):
+            r = rows[L, k]
+            r = r[r[:, 1] != 0]
+            if r.size == 0:
+                continue
+            t0, t1 = r[:, 0].astype(np.float64), r[:, 1].astype(np.float64)
+            row[name + "_us"] = round((t1.max() - t0.min()) / mhz, 1)
+            if k == 1:
+                wg = (t1 - t0) / mhz
+                row["child_wg_mean_us"] = round(float(wg.mean()), 1)
+                row["child_wg_max_us"] = round(float(wg.max()), 1)
+                row["child_exit_spread_us"] = round(float(t1.max() - t1.min()) / mhz, 1)
+                row["child_workgroups"] = int(r.shape[0])
+        if len(row) > 1:
+            out.append(row)
+    return out
+
+
 def bench_breakdown(args, dpo, torch):
     """Sec. VIII-B: parent / aggregation / launch / disaggregation / child time
     per traversal at CF 1, 2, 4, 8 and a few thresholds, from the timed
@@ -1159,6 +1184,7 @@ def bench_breakdown(args, dpo, torch):
     stream = torch.cuda.current_stream()
     phases = ("parent", "aggregation", "launch", "disaggregation", "child", "gaps")
     results = []
+    levels_of = None  # per-level table of the tuned options' first source
     for CF in (1, 2, 4, 8):
         for T in Ts:
             o = dpo.Options(**{**tuned, "threshold": T, "coarsen": CF, "steps_per_replay": steps})
@@ -1177,6 +1203,8 @@ def bench_breakdown(args, dpo, torch):
                 tot, per_level, ib = phase_split(rows)
                 skews.append(child_skew(rows))
                 grids = [int((rows[:, k, :, 1] != 0).sum(axis=1).max()) for k in range(3)]
+                if levels_of is None and T == tuned["threshold"] and CF == tuned["coarsen"]:
+                    levels_of = (int(s), level_table(rows))
                 for p in phases:
                     acc[p] += tot[p] / len(wl.sources)
                 imb.append(ib)
@@ -1236,6 +1264,13 @@ def bench_breakdown(args, dpo, torch):
     md += ["", "Workgroups that stamped rows (largest level; parent, child, thresholded-children "
            "kernel): " + "; ".join(f"T{r['threshold']} CF{r['coarsen']}: {r['workgroups_with_rows']}"
                                    for r in results[:3]) + "."]
+    if levels_of is not None:
+        src, table = levels_of
+        cols = ["level", "parent_us", "child_us", "serial_us", "child_wg_mean_us", "child_wg_max_us",
+                "child_exit_spread_us", "child_workgroups"]
+        md += ["", f"## Per level, tuned options ({tuned['threshold']}, CF {tuned['coarsen']}), "
+                   f"source {src}", "", "| " + " | ".join(cols) + " |", "|" + "---|" * len(cols)]
+        md += ["| " + " | ".join(str(r.get(c, "")) for c in cols) + " |" for r in table]
     md += ["", "## Longest level of any source (us)", "",
            "| T | CF | level | parent | aggregation | launch | disaggregation | child | gaps |",
            "|---|---|---|---|---|---|---|---|---|"]
@@ -1258,7 +1293,7 @@ def sweep(dpo, torch, wl, dg, cmd):
     import itertools
     import platform
     tuned = TUNED[wl.name]
-    fixed = {k: tuned[k] for k in ("child_block", "split_min") if k in tuned}
+    fixed = {k: tuned[k] for k in ("child_block", "split_min", "dyn_share") if k in tuned}
     rs, _ = reached_stats(dpo, torch, wl, dg, dpo.Options(**{**tuned, "steps_per_replay": 0}))
     edges = float(sum(r[0] for r in rs) / 2)
     steps = max(r[2]["levels"] for r in rs) + 1
@@ -1284,6 +1319,7 @@ def sweep(dpo, torch, wl, dg, cmd):
     best = max(nested)
     md = [f"# {wl.name}: threshold x coarsening x granularity sweep", "",
           f"Workload: {wl.desc} (n = {wl.g.n}, m = {wl.g.m}).  Child block {fixed.get('child_block', 256)}"
+          f", dyn_share {fixed.get('dyn_share', 0)}"
           f"{', one visited copy below ' + str(fixed['split_min']) + ' frontier entries' if 'split_min' in fixed else ''}; "
           f"{steps} level steps per replay; each point 1 warm-up + 2 timed passes over the "
           f"{len(wl.sources)} source(s), hipEvents around each call.  GTEPS = undirected edges "

@@ -1099,6 +1099,12 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
     dyn1 = r1;
     csz = max(1u, (dyn1 - dyn0) / (2u * nwx));  // about two chunks per wave
   }
+  // wave-uniform by construction (scalar registers)
+  t0 = __builtin_amdgcn_readfirstlane(t0);
+  t1 = __builtin_amdgcn_readfirstlane(t1);
+  dyn0 = __builtin_amdgcn_readfirstlane(dyn0);
+  dyn1 = __builtin_amdgcn_readfirstlane(dyn1);
+  csz = __builtin_amdgcn_readfirstlane(csz);
   Counters cn{0, 0, 0, 0, 0, 0, 0};
   Stage s{s_stage[wave], 0u};
   pc.mark(TP_LAUNCH);  // reading the level's published grids
@@ -1203,7 +1209,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
     if (failed || dyn0 >= dyn1) break;
     uint32_t j = 0;
     if (lane == 0) j = atomicAdd(&cur->cclaim[xg][0], 1u);
-    j = __shfl(j, 0, 64);
+    j = __builtin_amdgcn_readfirstlane(j);
     const uint64_t c0 = (uint64_t)dyn0 + (uint64_t)j * csz;
     if (c0 >= dyn1) break;
     t0 = (uint32_t)c0;
