@@ -837,7 +837,7 @@ def bench_batch(args, dpo, torch, full_line=False):
            "tuning_runs": [len(t) for t in traces],
            "tuning_trace": {"threshold_coarsening_per_bucket": [
                                 {lbl: round(v * 1e3, 3) for lbl, v in t} for t in traces],
-                            "granularity_ms": {lbl: round(v * 1e3, 3) for lbl, v in gtrace}}}
+                            "granularity_then_check_ms": {lbl: round(v * 1e3, 3) for lbl, v in gtrace}}}
     # a sample of the same queries, one dpo_bfs call each on its own graph
     one = dpo.Options(threshold=32, coarsen=1, steps_per_replay=16, child_block=128)
     sub = qs[::8]

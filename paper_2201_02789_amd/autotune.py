@@ -14,7 +14,11 @@ to the best.  The tuner follows that in two stages:
    neighbour is faster or after `max_runs` timed points;
 2. aggregation granularity, for the whole launch: block, 4-block, 16-block
    and grid (wave is skipped, as the paper finds it never best), timing the
-   whole batch with every bucket at its stage-1 point.
+   whole batch with every bucket at its stage-1 point;
+3. a check on the whole batch: each bucket in turn goes back to the base
+   (T, CF) and keeps it when the whole batch is faster that way (a bucket's
+   best point timed alone need not be best beside the others, and stage-1
+   differences can be within timing noise).
 
 Granularity is a property of the launch, not of a bucket: the parent
 workgroups' frontier entries mix queries of every bucket, and aggregation
@@ -147,7 +151,28 @@ def tune(kind, arena, graphs, queries, bucket_of_graph, nbuckets, base: dpo.Opti
         traces.append(tr)
     qs = [(g, s, bucket_of_graph[g]) for g, s in queries]
     opts, gtrace = tune_granularity(kind, arena, qs, opts, log)
-    return opts, traces, gtrace
+    opts, ctrace = check_against_base(kind, arena, qs, opts, base, log)
+    return opts, traces, gtrace + ctrace
+
+
+def check_against_base(kind, arena, queries, bucket_opts, base: dpo.Options, log=None, reps=3):
+    """Stage 3: per bucket, the whole batch with that bucket back at the base
+    threshold and coarsening; kept when faster.  Returns (Options, trace)."""
+    cur = list(bucket_opts)
+    best = _time_batch(kind, arena, queries, cur, reps)
+    trace = [("tuned", best)]
+    for b, o in enumerate(cur):
+        if (o.threshold, o.coarsen) == (base.threshold, base.coarsen):
+            continue
+        cand = list(cur)
+        cand[b] = dpo.Options(**{**asdict(o), "threshold": base.threshold, "coarsen": base.coarsen})
+        t = _time_batch(kind, arena, queries, cand, reps)
+        trace.append((f"bucket{b}-base", t))
+        if log:
+            log(f"[tune] {kind} bucket {b} at the base point: {t * 1e3:.3f} ms (tuned {best * 1e3:.3f})")
+        if t < best:
+            cur, best = cand, t
+    return cur, trace
 
 
 def save(path, opts, meta=None):

@@ -39,8 +39,29 @@ def test_greedy_walk_and_granularity_stage(monkeypatch):
     assert (opts[0].threshold, opts[0].coarsen) == (128, 2)
     assert (opts[0].agg, opts[0].agg_blocks) == (dpo.DPO_AGG_MULTIBLOCK, 16)
     assert opts[0].child_block == 128
-    assert [n for n, _ in gtrace] == ["block", "4-block", "16-block", "grid"]
+    assert [n for n, _ in gtrace][:4] == ["block", "4-block", "16-block", "grid"]
+    assert gtrace[4][0] == "tuned" and gtrace[5][0] == "bucket0-base"
     assert len(traces) == 1 and len(traces[0]) <= 20
     # a bucket without queries keeps the base point
     opts2, traces2, _ = autotune.tune("bfs", None, graphs, queries, [0, 0], 2, base, max_runs=4)
     assert traces2[1] == [] and opts2[1].threshold == base.threshold
+
+
+def test_check_stage_reverts_a_bucket_that_loses_on_the_whole_batch(monkeypatch):
+    """Stage 3: a bucket whose stage-1 point is slower on the whole batch than
+    the base point goes back to the base point; one that is faster keeps it."""
+    calls = []
+
+    def fake_time(kind, arena, qs, opts, reps=2):
+        bopts = opts if isinstance(opts, (list, tuple)) else [opts]
+        calls.append([o.threshold for o in bopts])
+        # bucket 0 at T=128 costs more than at the base T=32; bucket 1 at 128 less
+        return sum({(0, 128): 3.0, (0, 32): 1.0, (1, 128): 1.0, (1, 32): 2.0}[(b, o.threshold)]
+                   for b, o in enumerate(bopts))
+
+    monkeypatch.setattr(autotune, "_time_batch", fake_time)
+    base = dpo.Options(threshold=32, coarsen=1)
+    tuned = [dpo.Options(threshold=128, coarsen=1), dpo.Options(threshold=128, coarsen=1)]
+    out, trace = autotune.check_against_base("bfs", None, [(0, 0, 0), (1, 0, 1)], tuned, base)
+    assert [o.threshold for o in out] == [32, 128]
+    assert [n for n, _ in trace] == ["tuned", "bucket0-base", "bucket1-base"]
