@@ -63,6 +63,8 @@ def parse():
                         "profiles/primitives.md")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 512 MiB device copy (counter calibration)")
+    p.add_argument("--summarize-counters", metavar="DIR", default=None,
+                   help="write profiles/<workload>_counters.md from the counter passes under DIR")
     p.add_argument("--summarize-profiles", metavar="DIR", default=None,
                    help="write profiles/<workload>_kernels.md and _traffic.json from the "
                         "rocprofv3 CSV output under DIR (trace/, fetch/, write/, "
@@ -430,6 +432,79 @@ def _short(name):
     return name.split("(")[0].replace("void ", "").replace("dpo::", "")
 
 
+# counter passes of --summarize-counters (each within the per-block limits of
+# one rocprofv3 --pmc run: at most 8 SQ, 4 TCP, 2 TA and 2 GRBM counters)
+COUNTER_PASSES = [
+    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_WAIT_ANY SQ_ACTIVE_INST_VALU "
+    "SQ_ACTIVE_INST_VMEM SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE",
+    "SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_LDS SQ_INSTS_SMEM "
+    "SQ_INSTS_BRANCH SQ_INST_LEVEL_VMEM",
+    "TA_BUSY_avr TA_ADDR_STALLED_BY_TC_CYCLES_sum TCP_PENDING_STALL_CYCLES_sum TCP_TCC_READ_REQ_sum "
+    "TCP_TCC_READ_REQ_LATENCY_sum TCP_TCR_TCP_STALL_CYCLES_sum GRBM_GUI_ACTIVE GRBM_TA_BUSY",
+    "TCP_UTCL1_STALL_INFLIGHT_MAX_sum TCP_READ_TAGCONFLICT_STALL_CYCLES_sum "
+    "TCP_TCC_ATOMIC_WITH_RET_REQ_sum TCP_TD_TCP_STALL_CYCLES_sum TA_DATA_STALLED_BY_TC_CYCLES_sum "
+    "TA_TA_BUSY_sum"]
+
+
+def summarize_counters(args, d):
+    """Where the level kernels' waves spend their time, from the counter passes
+    under d (<workload>_p1 .. _p4, one rocprofv3 --pmc run each): issue and
+    wait shares of wave time, wave instructions per edge run, average L2 read
+    latency, texture-addresser busy share."""
+    import csv
+    import glob
+    name = args.workload
+    extra = "" if name == "bfs22" else f" --workload {name}"
+    agg, trav = {}, {}
+    for i in range(1, len(COUNTER_PASSES) + 1):
+        files = glob.glob(os.path.join(d, f"{name}_p{i}", "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter CSV for pass {i} under {d}")
+        ncnt = len(COUNTER_PASSES[i - 1].split())
+        inits = 0
+        for r in csv.DictReader(open(files[0])):
+            n = _short(r["Kernel_Name"])
+            if n == "init_kernel":
+                inits += 1
+            if n.startswith(("parent_kernel", "child_kernel")):
+                c = agg.setdefault(n, {})
+                c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        trav[i] = inits / ncnt  # one row per counter per dispatch
+    # edges run per traversal: the bench line that the first pass's run printed
+    with open(os.path.join(d, f"{name}_p1.out")) as f:
+        line = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    edges = line["roofline_probe"]["probes_per_traversal"]
+    md = [f"# {name}: where the level kernels' waves spend their time (rocprofv3 counters)", "",
+          "Commands (MI355X, repository root, after `export TMPDIR=/tmp`), one run per pass:", "", "```"]
+    md += [f"rocprofv3 --pmc {p} --output-format csv -d {d}/{name}_p{i + 1} -o c -- python3 bench.py"
+           f"{extra} --no-cpu --no-extras --no-baselines --steps 1 --warmup 1 > {d}/{name}_p{i + 1}.out"
+           for i, p in enumerate(COUNTER_PASSES)]
+    md += [f"python3 bench.py{extra} --summarize-counters {d}", "```", "",
+           f"Traversals per run: {trav[1]:.0f}; edges run per traversal {edges:.0f}.  Shares are of "
+           "SQ_WAVE_CYCLES (the waves' resident time); per-edge counts are wave instructions "
+           "(one per 64 lanes).", "",
+           "| kernel | issuing any / VALU | waiting on memory (WAIT_INST_ANY) | waiting on anything (WAIT_ANY) | "
+           "VALU / SALU / VMEM-read / LDS / branch per edge | L2 read latency (cycles) | TA busy |",
+           "|---|---|---|---|---|---|---|"]
+    for n, c in sorted(agg.items()):
+        wc = max(c.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        per = edges * trav[2]
+        md.append(f"| {n} | {c['SQ_ACTIVE_INST_ANY'] / wc:.3f} / {c['SQ_ACTIVE_INST_VALU'] / wc:.3f} | "
+                  f"{c['SQ_WAIT_INST_ANY'] / wc:.3f} | {c['SQ_WAIT_ANY'] / wc:.3f} | "
+                  f"{c['SQ_INSTS_VALU'] / per:.2f} / {c['SQ_INSTS_SALU'] / per:.2f} / "
+                  f"{c['SQ_INSTS_VMEM_RD'] / per:.3f} / {c['SQ_INSTS_LDS'] / per:.3f} / "
+                  f"{c['SQ_INSTS_BRANCH'] / per:.3f} | "
+                  f"{c['TCP_TCC_READ_REQ_LATENCY_sum'] / max(c['TCP_TCC_READ_REQ_sum'], 1):.0f} | "
+                  f"{c['TA_BUSY_avr'] / max(c['GRBM_GUI_ACTIVE'], 1):.3f} |")
+    md += ["", "Raw sums over the run's dispatches:", "", "| kernel | counter | value |", "|---|---|---|"]
+    for n, c in sorted(agg.items()):
+        md += [f"| {n} | {k} | {v:.4g} |" for k, v in sorted(c.items())]
+    out = os.path.join(ROOT, "profiles", f"{name}_counters.md")
+    with open(out, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(json.dumps({"wrote": out}))
+
+
 def summarize_profiles(args, d):
     """Level-step kernel time from a kernel trace and HBM bytes from FETCH_SIZE
     / WRITE_SIZE counter runs, each counter scaled by what it reads for a plain
@@ -719,6 +794,8 @@ def main():
     args = parse()
     if args.summarize_profiles:
         return summarize_profiles(args, args.summarize_profiles)
+    if args.summarize_counters:
+        return summarize_counters(args, args.summarize_counters)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "(independent traversals shard by graph across GPUs)", file=sys.stderr)
