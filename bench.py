@@ -48,6 +48,7 @@ def parse():
                    help="frontier size from which a level uses two visited copies")
     p.add_argument("--agg", default=None, help="none|wave|block|<k>-block")
     p.add_argument("--serial-wave", type=int, default=None, choices=[0, 1])
+    p.add_argument("--child-block", type=int, default=None, choices=[64, 128, 256])
     p.add_argument("--dyn-share", type=int, default=None,
                    help="percent of the child blocks claimed in chunks (0 = even split)")
     p.add_argument("--breakdown", action="store_true",
@@ -655,6 +656,8 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
         tuned["serial_wave"] = args.serial_wave
     if overrides and args.dyn_share is not None:
         tuned["dyn_share"] = args.dyn_share
+    if overrides and args.child_block is not None:
+        tuned["child_block"] = args.child_block
     a = agg_of(args.agg) if overrides else None
     if a:
         tuned["agg"], tuned["agg_blocks"] = a

@@ -101,3 +101,46 @@ def test_child_skew_on_known_rows():
     assert abs(sk["xcd_span_ratio"] - 2.0) < 1e-9
     t1 = [100 + (w % 11) + (200 if w % 8 == 3 else 100) for w in range(16)]
     assert abs(sk["end_spread_us"] - (max(t1) - min(t1)) / 100) < 1e-9
+
+
+def test_summarize_counters_on_synthetic_passes(tmp_path, monkeypatch):
+    """The counter summary divides by the traversal count of each pass (one CSV
+    row per counter per dispatch) and by the edges of the run's bench line."""
+    import csv
+    import json
+
+    d = tmp_path / "sq"
+    edges = 1000.0
+    for i, passes in enumerate(bench.COUNTER_PASSES, start=1):
+        names = passes.split()
+        pd = d / f"bfs22_p{i}"
+        pd.mkdir(parents=True)
+        with open(pd / "c_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name",
+                                              "Counter_Value"])
+            w.writeheader()
+            for t in range(2):  # two traversals: init, parent, child dispatches
+                for k, kern in enumerate(("dpo::init_kernel(dpo::Args)",
+                                          "void dpo::child_kernel<0, false>(dpo::Args, unsigned int)")):
+                    for c in names:
+                        val = {"SQ_WAVE_CYCLES": 1000.0, "SQ_WAIT_INST_ANY": 500.0,
+                               "SQ_INSTS_VALU": 300.0, "TCP_TCC_READ_REQ_sum": 10.0,
+                               "TCP_TCC_READ_REQ_LATENCY_sum": 4000.0}.get(c, 1.0)
+                        w.writerow({"Dispatch_Id": 10 * t + k, "Kernel_Name": kern,
+                                    "Counter_Name": c, "Counter_Value": val})
+        (d / f"bfs22_p{i}.out").write_text(json.dumps(
+            {"roofline_probe": {"probes_per_traversal": edges}}) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+
+    class A:
+        workload = "bfs22"
+
+    bench.summarize_counters(A(), str(d))
+    md = (tmp_path / "profiles" / "bfs22_counters.md").read_text()
+    row = [ln for ln in md.splitlines() if ln.startswith("| child_kernel<0, false>") and "/" in ln][0]
+    cells = [c.strip() for c in row.strip("|").split("|")]
+    assert cells[2] == "0.500"                  # waiting share: 2 x 500 / 2 x 1000
+    assert cells[4].startswith("0.30 /")        # VALU per edge: 2 x 300 / (2 traversals x 1000)
+    assert cells[5] == "400"                    # L2 read latency: 8000 / 20
+    assert "Traversals per run: 2;" in md
