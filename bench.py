@@ -64,6 +64,9 @@ def parse():
                         "profiles/primitives.md")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 512 MiB device copy (counter calibration)")
+    p.add_argument("--simulate-bands", action="store_true",
+                   help="host simulation of a near-far band split of the s21 SSSP levels; "
+                        "writes profiles/sssp21_bands.md (no GPU)")
     p.add_argument("--summarize-counters", metavar="DIR", default=None,
                    help="write profiles/<workload>_counters.md from the counter passes under DIR")
     p.add_argument("--summarize-profiles", metavar="DIR", default=None,
@@ -447,6 +450,68 @@ COUNTER_PASSES = [
     "TA_TA_BUSY_sum"]
 
 
+def simulate_bands(deltas=(32, 64, 128, 256, 512)):
+    """Host simulation (numpy, no GPU) of synchronous frontier Bellman-Ford on
+    the s21 SSSP graph, plain and with a near-far band split of width delta:
+    an improved vertex whose distance is at or above the current band's upper
+    bound is not expanded; when no frontier is left, the next band's vertices
+    are selected by a scan of all distances.  Counts the edges relaxed and the
+    levels (scan levels included), the quantities that decide whether deferral
+    could pay on this graph.  Writes profiles/sssp21_bands.md."""
+    from paper_2201_02789_amd import graphgen as gg
+    g = gg.add_weights(gg.rmat(21, 16, 21, perm_seed=24), 31)
+    rp = g.row_ptr.astype(np.int64)
+    col = g.col_idx.astype(np.int64)
+    w = g.weights.astype(np.int64)
+    n, src, inf = g.n, int(gg.max_degree_vertex(g)), np.int64(1) << 40
+
+    def run(delta):
+        d = np.full(n, inf)
+        d[src] = 0
+        front, bound = np.array([src], np.int64), (delta or inf)
+        relaxed = levels = scans = deferred = 0
+        while True:
+            levels += 1
+            if len(front) == 0:
+                if not delta:
+                    break
+                lo, bound = bound, bound + delta  # every finite d >= lo is pending
+                scans += 1
+                front = np.nonzero((d >= lo) & (d < bound))[0]
+                if len(front) == 0 and not np.any((d >= bound) & (d < inf)):
+                    break
+                continue
+            near = d[front] < bound
+            deferred += int(np.count_nonzero(~near))
+            fr = front[near]
+            deg = rp[fr + 1] - rp[fr]
+            relaxed += int(deg.sum())
+            e = np.repeat(rp[fr] - (np.cumsum(deg) - deg), deg) + np.arange(int(deg.sum()))
+            old = d.copy()
+            np.minimum.at(d, col[e], np.repeat(d[fr], deg) + w[e])
+            front = np.nonzero(d < old)[0]
+        return relaxed, levels, scans, deferred, d
+
+    base = run(0)
+    reached = base[4] < inf
+    m_reached = int((rp[1:] - rp[:-1])[reached].sum())
+    rows = [("plain", base)] + [(str(dl), run(dl)) for dl in deltas]
+    for _, r in rows:
+        assert np.array_equal(r[4], base[4])
+    md = ["# sssp21: synchronous frontier Bellman-Ford with a near-far band split (host simulation)",
+          "", "Command (repository root): `python3 bench.py --simulate-bands` (numpy, no GPU).", "",
+          f"Graph: R-MAT scale 21, edgefactor 16, weights U[1,255], max-degree source; "
+          f"{m_reached / 1e6:.1f} M edges out of reached vertices, largest distance "
+          f"{int(base[4][reached].max())}.  Every row reaches the same distances.", "",
+          "| band width | edges relaxed (M) | per reached edge | levels | scan levels | deferred entries (M) |",
+          "|---|---|---|---|---|---|"]
+    md += [f"| {k} | {r[0] / 1e6:.1f} | {r[0] / m_reached:.2f} | {r[1]} | {r[2]} | {r[3] / 1e6:.2f} |"
+           for k, r in rows]
+    with open(os.path.join(ROOT, "profiles", "sssp21_bands.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    return {k: {"relaxed": r[0], "levels": r[1], "scans": r[2]} for k, r in rows}
+
+
 def summarize_counters(args, d):
     """Where the level kernels' waves spend their time, from the counter passes
     under d (<workload>_p1 .. _p4, one rocprofv3 --pmc run each): issue and
@@ -799,6 +864,9 @@ def main():
         return summarize_profiles(args, args.summarize_profiles)
     if args.summarize_counters:
         return summarize_counters(args, args.summarize_counters)
+    if args.simulate_bands:
+        print(json.dumps(simulate_bands()), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "(independent traversals shard by graph across GPUs)", file=sys.stderr)
