@@ -99,7 +99,8 @@ def agg_of(s):
 # blockDim, which the naive baseline shares) is 128 lanes on the large
 # workloads: the child kernel splits a level's blocks evenly over its waves,
 # and smaller blocks make equal block counts closer to equal edge counts.
-TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128, dyn_share=25),
+TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128, dyn_share=25,
+                       split_min=4096),
          "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
@@ -337,6 +338,9 @@ def calib_lib():
         L.dpo_calib_workgroup_atomics.argtypes = [vp, u32, u32, i32, vp]
         L.dpo_calib_workgroup_placement.argtypes = [i32, i32, vp, vp]
         L.dpo_calib_random_coherent_loads.argtypes = [vp, u32, u32, i32, vp, vp]
+        L.dpo_calib_random_atomic_or_ret.argtypes = [vp, u32, u32, i32, vp, vp]
+        L.dpo_calib_random_stores.argtypes = [vp, u32, u32, i32, vp]
+        L.dpo_calib_loads_and_atomics.argtypes = [vp, vp, u32, u32, u32, u32, i32, vp, vp]
         _calib = L
     return _calib
 
@@ -399,6 +403,29 @@ def calibrate_primitives(torch):
         t = torch.zeros(words, dtype=torch.int32, device="cuda")
         ms = _timed(torch, lambda st: L.dpo_calib_random_atomic_or(t.data_ptr(), words, 8, grid, st))
         res[f"random_atomic_or_{kb}KiB_G_per_s"] = round(grid * 256 * 8 * 8 / (ms * 1e-3) / 1e9, 2)
+    for kb in (512, 16 << 10):
+        words = (kb << 10) // 4
+        t = torch.zeros(words, dtype=torch.int32, device="cuda")
+        ms = _timed(torch, lambda st: L.dpo_calib_random_atomic_or_ret(t.data_ptr(), words, 8, grid,
+                                                                       out.data_ptr(), st))
+        res[f"random_atomic_or_returning_{kb}KiB_G_per_s"] = round(grid * 256 * 8 * 8 / (ms * 1e-3) / 1e9, 2)
+        ms = _timed(torch, lambda st: L.dpo_calib_random_stores(t.data_ptr(), words, 16, grid, st))
+        res[f"random_store_{kb}KiB_G_per_s"] = round(grid * 256 * 16 * 8 / (ms * 1e-3) / 1e9, 1)
+    # loads of a 512 KiB table by 15 of every 16 workgroups, while the 16th
+    # run returning atomics on the same table or on a second one
+    words, every, it = 1 << 17, 16, 16
+    lt = torch.zeros(words, dtype=torch.int32, device="cuda")
+    at = torch.zeros(words, dtype=torch.int32, device="cuda")
+    loads = (grid - (grid + every - 1) // every) * 256 * it * 8
+    for key, tbl, mode in (("loads_alone", lt, 1), ("atomics_alone", lt, 2),
+                           ("loads_with_atomics_same_table", lt, 3),
+                           ("loads_with_atomics_other_table", at, 3)):
+        ms = _timed(torch, lambda st: L.dpo_calib_loads_and_atomics(lt.data_ptr(), tbl.data_ptr(), words,
+                                                                    it, every, mode, grid,
+                                                                    out.data_ptr(), st))
+        res[f"mixed_512KiB_{key}_ms"] = round(ms, 4)
+        if mode != 2:
+            res[f"mixed_512KiB_{key}_load_G_per_s"] = round(loads / (ms * 1e-3) / 1e9, 1)
     # where workgroups run: the XCC id each one reads from its hardware
     # register, against workgroup % 8 (round-robin placement over the XCDs)
     for g in (2048, 4096):

@@ -107,7 +107,22 @@ typedef struct {
                                left (as a hardware block scheduler hands out
                                blocks), so waves whose blocks run slow do fewer.
                                Speed only.                                      */
+  int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  BFS levels
+                               with two visited copies: before its claim atomic,
+                               a lane checks and sets its vertex's bit in a
+                               bitmap private to its XCD (workgroup % 8) with
+                               plain loads and stores, so that each XCD sends at
+                               most one claim per vertex and no device-coherent
+                               load of the claimed copy is needed.  Speed only. */
 } dpo_options;
+
+typedef enum {
+  DPO_HINT_AUTO = 0,  /* on while the visited bitmap is at most 1 MiB (8 M
+                         vertices), so that it and the XCD's bitmap share the
+                         XCD's L2                                              */
+  DPO_HINT_ON = 1,
+  DPO_HINT_OFF = 2
+} dpo_claim_hint;
 
 typedef struct {
   int32_t n;                /* vertices, >= 1                                      */

@@ -8,7 +8,11 @@
 //   a streaming read of int32 and of int4 elements (the col_idx stream);
 //   a streaming int32 read with one dependent probe of a table per element
 //     (the child body: v = col[e], then visited[v]);
-//   random atomicOr on a table (the BFS claim);
+//   random atomicOr on a table (the BFS claim), with and without its return;
+//   random plain stores (the level writes, the claim hints);
+//   random loads of a table while some workgroups update it, or a second
+//     table, with atomics (a probed bitmap that is also claimed in, against
+//     probed and claimed copies);
 //   atomics of every workgroup on one address (a shared queue counter).
 //
 // Every index is masked into its buffer (table sizes are powers of two) or
@@ -143,6 +147,63 @@ __global__ __launch_bounds__(256) void random_atomic_or(uint32_t* __restrict__ t
   }
 }
 
+// The same, returning each old word (summed into out, so none is dead).
+__global__ __launch_bounds__(256) void random_atomic_or_ret(uint32_t* __restrict__ table, uint32_t mask,
+                                                            uint32_t iters, uint32_t* __restrict__ out) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t x = tid * 0x9E3779B9u + 0x2545F491u, acc = 0;
+  for (uint32_t i = 0; i < iters; ++i) {
+    uint32_t r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x = xorshift(x);
+      r[u] = atomicOr(&table[x & mask], 1u << (x >> 27));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += r[u];
+  }
+  out[tid] = acc;
+}
+
+// iters x 8 plain stores per lane at pseudo-random words of the table.
+__global__ __launch_bounds__(256) void random_stores(uint32_t* __restrict__ table, uint32_t mask,
+                                                     uint32_t iters) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t x = tid * 0x9E3779B9u + 0x68E31DA4u;
+  for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x = xorshift(x);
+      table[x & mask] = x;
+    }
+  }
+}
+
+// Workgroups w with w % every == 0 run iters x 8 returning atomicOr on `at`
+// (if mode & 2), the others iters x 8 loads of `lt` (if mode & 1); a part
+// whose bit is clear returns at once.  `at` may be `lt` or another table of
+// the same size.
+__global__ __launch_bounds__(256) void loads_and_atomics(const uint32_t* __restrict__ lt,
+                                                         uint32_t* __restrict__ at, uint32_t mask,
+                                                         uint32_t iters, uint32_t every, uint32_t mode,
+                                                         uint32_t* __restrict__ out) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool atom = blockIdx.x % every == 0;
+  if (atom ? !(mode & 2u) : !(mode & 1u)) return;
+  uint32_t x = tid * 0x9E3779B9u + 0x1B873593u, acc = 0;
+  for (uint32_t i = 0; i < iters; ++i) {
+    uint32_t r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x = xorshift(x);
+      r[u] = atom ? atomicOr(&at[x & mask], 1u << (x >> 27)) : lt[x & mask];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += r[u];
+  }
+  out[tid] = acc;
+}
+
 // One lane per workgroup adds `iters` times to one of `naddr` counters
 // (workgroup % naddr): same-address atomics serialise at the L2.
 __global__ __launch_bounds__(64) void workgroup_atomics(uint32_t* __restrict__ ctr, uint32_t naddr,
@@ -220,6 +281,36 @@ int dpo_calib_random_atomic_or(uint32_t* table, uint32_t table_words, uint32_t i
   if (!table || grid < 1 || table_words == 0 || (table_words & (table_words - 1))) return -1;
   hipLaunchKernelGGL(random_atomic_or, dim3(grid), dim3(256), 0, (hipStream_t)stream, table,
                      table_words - 1, iters);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// out: device uint32[grid * 256] (ret != 0 only).
+int dpo_calib_random_atomic_or_ret(uint32_t* table, uint32_t table_words, uint32_t iters, int grid,
+                                   uint32_t* out, void* stream) {
+  if (!table || !out || grid < 1 || table_words == 0 || (table_words & (table_words - 1))) return -1;
+  hipLaunchKernelGGL(random_atomic_or_ret, dim3(grid), dim3(256), 0, (hipStream_t)stream, table,
+                     table_words - 1, iters, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int dpo_calib_random_stores(uint32_t* table, uint32_t table_words, uint32_t iters, int grid,
+                            void* stream) {
+  if (!table || grid < 1 || table_words == 0 || (table_words & (table_words - 1))) return -1;
+  hipLaunchKernelGGL(random_stores, dim3(grid), dim3(256), 0, (hipStream_t)stream, table,
+                     table_words - 1, iters);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// lt, at: device uint32[table_words] (may be the same buffer); out: device
+// uint32[grid * 256]; every >= 1; mode in 1..3.
+int dpo_calib_loads_and_atomics(const uint32_t* lt, uint32_t* at, uint32_t table_words,
+                                uint32_t iters, uint32_t every, uint32_t mode, int grid,
+                                uint32_t* out, void* stream) {
+  if (!lt || !at || !out || grid < 1 || every < 1 || mode < 1 || mode > 3 || table_words == 0 ||
+      (table_words & (table_words - 1)))
+    return -1;
+  hipLaunchKernelGGL(loads_and_atomics, dim3(grid), dim3(256), 0, (hipStream_t)stream, lt, at,
+                     table_words - 1, iters, every, mode, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -83,7 +83,8 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
   L.front0 = off; off = align_up(off + fslots * 4);
   L.front1 = off; off = align_up(off + fslots * 4);
-  L.visit = off; off = align_up(off + (size_t)slots * 4);  // SSSP stamps / two BFS bitmaps
+  // SSSP stamps / two BFS bitmaps and the NHINT claim hints
+  L.visit = off; off = align_up(off + std::max((size_t)slots, (size_t)(2 + NHINT) * cdiv(slots, 32)) * 4);
   L.dist2 = off; off = align_up(off + (size_t)slots * 4);  // SSSP second distance array
   L.rec = off; off = align_up(off + (size_t)slots * 16);
   L.rec_q = off; off = align_up(off + (size_t)slots * 4);
@@ -106,6 +107,7 @@ dpo_status check_options(const dpo_options& o) {
   if (o.split_min < 0) return DPO_ERR_ARG;
   if (o.serial_wave != 0 && o.serial_wave != 1) return DPO_ERR_ARG;
   if (o.dyn_share < 0 || o.dyn_share > 100) return DPO_ERR_ARG;
+  if (o.claim_hint < DPO_HINT_AUTO || o.claim_hint > DPO_HINT_OFF) return DPO_ERR_ARG;
   if (o.agg == DPO_AGG_MULTIBLOCK && (o.agg_blocks < 2 || o.agg_blocks > 1024)) return DPO_ERR_ARG;
   if (o.child_block != 64 && o.child_block != 128 && o.child_block != 256) return DPO_ERR_ARG;
   if (o.steps_per_replay < 0 || o.steps_per_replay > 1024) return DPO_ERR_ARG;
@@ -334,6 +336,9 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.split_min = o.split_min;
   a.serial_wave = o.serial_wave;
   a.dyn_pct = o.dyn_share;
+  a.hint = problem == PROB_BFS &&
+           (o.claim_hint == DPO_HINT_ON ||
+            (o.claim_hint == DPO_HINT_AUTO && (uint64_t)a.vwords <= HINT_MAX_WORDS));
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
@@ -946,6 +951,7 @@ void dpo_default_options(dpo_options* o) {
   o->split_min = 65536;
   o->serial_wave = 1;
   o->dyn_share = 0;
+  o->claim_hint = DPO_HINT_AUTO;
 }
 
 size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o) {

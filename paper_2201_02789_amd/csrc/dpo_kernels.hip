@@ -250,21 +250,48 @@ __device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const
     uint32_t word[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? pb[(uint32_t)sl[u] >> 5] : ~0u;
-    // split level: vertices found earlier in this level are still clear in
-    // the probed bitmap.  When a batch has many candidates, a coherent load of
-    // the claim word skips their atomics; with few, the extra round trip would
-    // only add latency.
-    uint32_t ncand = 0;
+    // Split level: vertices found earlier in this level are still clear in
+    // the probed bitmap, and many edges lead to each of them.  Loads of a line
+    // that device atomics are updating run several times slower than loads of
+    // a line no atomic touches, so the claimed bitmap is not read with plain
+    // loads.  With the claim hint, a candidate first tests and sets its bit in
+    // its XCD's own hint bitmap (plain loads and stores, which stay in that
+    // XCD's L2); a set bit means a lane of this XCD has sent or will send the
+    // claim, and the claim atomic decides the winner, so skipping is exact.
+    // The stores are not atomic: a lost bit only lets a second claim through.
+    // Without the hint, a batch with many candidates reads the claim words
+    // with coherent loads first; with few, that round trip would only add
+    // latency.  Either way a candidate's word is replaced by the word read,
+    // and the atomic below runs only where the bit is still clear.
+    bool filter = false;
     if (vis.split) {
+      if (a.hint) {
+        filter = true;
+      } else {
+        uint32_t ncand = 0;
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        ncand += (uint32_t)__popcll(__ballot(sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31)))));
+        for (int u = 0; u < U; ++u)
+          ncand += (uint32_t)__popcll(__ballot(sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31)))));
+        filter = ncand > PRECHECK_MIN;
+      }
     }
-    if (ncand > PRECHECK_MIN) {
+    if (filter) {
+      uint32_t* hb = a.visit + (size_t)(2u + (blockIdx.x & (NHINT - 1))) * (uint32_t)a.vwords;
+      if (a.hint) {
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31))))
-          word[u] = coherent_load(&cb[(uint32_t)sl[u] >> 5]);
+        for (int u = 0; u < U; ++u)
+          if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31)))) word[u] = hb[(uint32_t)sl[u] >> 5];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t bit = 1u << (sl[u] & 31);
+          if (sl[u] >= 0 && !(word[u] & bit)) hb[(uint32_t)sl[u] >> 5] = word[u] | bit;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31))))
+            word[u] = coherent_load(&cb[(uint32_t)sl[u] >> 5]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -508,6 +535,14 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   const uint32_t F = s_fpre[NQF + 1];
   if (F == 0) {
     if (PH != PH_SERIAL && blockIdx.x == 0 && tid == 0) st->done = 1;
+    return;
+  }
+  // Each vertex enters a frontier at most once per level (the claim atomic,
+  // the SSSP stamp), and the launch records, serial lists and group counters
+  // of a level are sized for that; a larger frontier is an error, never an
+  // index past them.
+  if (F > (uint32_t)a.slots) {
+    if (tid == 0) set_error(st, ERR_CAPACITY);
     return;
   }
   // visited copies of this level (every workgroup derives the same choice)
@@ -1278,6 +1313,8 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
       const uint32_t x = (i == src >> 5) ? (1u << (src & 31)) : 0u;
       a.visit[s0 / 32 + i] = x;  // both bitmaps hold the source
       a.visit[(size_t)a.vwords + s0 / 32 + i] = x;
+      if (a.hint)
+        for (uint32_t h = 0; h < (uint32_t)NHINT; ++h) a.visit[(size_t)(2 + h) * a.vwords + s0 / 32 + i] = 0u;
     }
   }
   if (reset) {

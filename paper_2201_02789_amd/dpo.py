@@ -31,6 +31,9 @@ DPO_AGG_WAVE = 1
 DPO_AGG_BLOCK = 2
 DPO_AGG_MULTIBLOCK = 3
 DPO_AGG_GRID = 4
+DPO_HINT_AUTO = 0
+DPO_HINT_ON = 1
+DPO_HINT_OFF = 2
 
 UNREACHED_LEVEL = -1
 UNREACHED_DIST = 0xFFFFFFFF
@@ -48,7 +51,7 @@ class _Options(ctypes.Structure):
                 ("agg_blocks", ctypes.c_int32), ("child_block", ctypes.c_int32),
                 ("steps_per_replay", ctypes.c_int32), ("agg_threshold", ctypes.c_int32),
                 ("split_min", ctypes.c_int32), ("serial_wave", ctypes.c_int32),
-                ("dyn_share", ctypes.c_int32)]
+                ("dyn_share", ctypes.c_int32), ("claim_hint", ctypes.c_int32)]
 
 
 class _Csr(ctypes.Structure):
@@ -87,6 +90,7 @@ class Options:
     split_min: int = 65536
     serial_wave: int = 1
     dyn_share: int = 0
+    claim_hint: int = 0  # DPO_HINT_AUTO
 
     def c(self) -> _Options:
         return _Options(*(int(getattr(self, f.name)) for f in fields(self)))
@@ -111,6 +115,7 @@ class Options:
         sm = f"-S{self.split_min}" if self.split_min != 65536 else ""
         sl = "-lane" if not self.serial_wave else ""
         sl += f"-D{self.dyn_share}" if self.dyn_share else ""
+        sl += {DPO_HINT_ON: "-H1", DPO_HINT_OFF: "-H0"}.get(self.claim_hint, "")
         cb = f"-CB{self.child_block}" if self.child_block != 256 else ""
         return f"T{self.threshold}-CF{self.coarsen}-{g}{cb}{at}{sm}{sl}"
 

@@ -49,6 +49,10 @@ def test_workspace_bytes_grows_and_rejects_bad_options():
     assert dpo.dpo_workspace_bytes(_G(1000, 10), dpo.Options(child_block=100)) == 0
     assert dpo.dpo_workspace_bytes(_G(1000, 10), dpo.Options(dyn_share=101)) == 0
     assert dpo.dpo_workspace_bytes(_G(1000, 10), dpo.Options(dyn_share=-1)) == 0
+    assert dpo.dpo_workspace_bytes(_G(1000, 10), dpo.Options(claim_hint=3)) == 0
+    assert dpo.dpo_workspace_bytes(_G(1000, 10), dpo.Options(claim_hint=-1)) == 0
+    for h in (dpo.DPO_HINT_AUTO, dpo.DPO_HINT_ON, dpo.DPO_HINT_OFF):
+        assert dpo.dpo_workspace_bytes(_G(1000, 10), dpo.Options(claim_hint=h)) > 0
     assert dpo.dpo_workspace_bytes(_G(0, 0), dpo.Options()) == 0
     # naive keeps one descriptor slot per parent: the largest workspace
     assert dpo.dpo_workspace_bytes(_G(10**5, 1), dpo.Options.naive()) > b

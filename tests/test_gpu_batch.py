@@ -58,7 +58,8 @@ MODES = [dict(), dict(agg=dpo.DPO_AGG_WAVE), dict(agg=dpo.DPO_AGG_BLOCK),
          dict(split_min=0), dict(split_min=256, steps_per_replay=3), dict(serial_wave=0),
          dict(child_block=128), dict(agg=dpo.DPO_AGG_GRID, child_block=128),
          dict(agg=dpo.DPO_AGG_NONE, child_block=128, split_min=0),
-         dict(child_block=128, dyn_share=25), dict(agg=dpo.DPO_AGG_NONE, dyn_share=100)]
+         dict(child_block=128, dyn_share=25), dict(agg=dpo.DPO_AGG_NONE, dyn_share=100),
+         dict(split_min=0, claim_hint=dpo.DPO_HINT_ON), dict(split_min=0, claim_hint=dpo.DPO_HINT_OFF)]
 
 
 @pytest.mark.parametrize("common", MODES, ids=[str(m) for m in MODES])

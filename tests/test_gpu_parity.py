@@ -192,16 +192,18 @@ def test_bfs_sweep_s14_permuted_several_sources(s14p):
             check_bfs_stats(g, want, opts, st)
 
 
+@pytest.mark.parametrize("hint", [dpo.DPO_HINT_ON, dpo.DPO_HINT_OFF], ids=["hint", "no-hint"])
 @pytest.mark.parametrize("split_min", [0, 512, 1 << 30], ids=["always-split", "switching", "never-split"])
-def test_visited_copies_every_mode(s14p, split_min):
+def test_visited_copies_every_mode(s14p, split_min, hint):
     """Levels that probe one visited copy and update the other, levels that use
     one copy, and traversals that switch between the two from level to level
     (split_min=512 on a scale-14 graph) give the oracle's results, with the
-    workspace reused across sources."""
+    workspace reused across sources; with and without the per-XCD claim hint
+    of the two-copy BFS levels."""
     g, dg = s14p
     srcs = [int(s) for s in gg.sample_sources(g, 3, 5)] + [gg.max_degree_vertex(g)]
     for base in (dpo.Options(threshold=32, coarsen=1), dpo.Options.naive(), dpo.Options.flat()):
-        opts = dpo.Options(**{**base.__dict__, "split_min": split_min})
+        opts = dpo.Options(**{**base.__dict__, "split_min": split_min, "claim_hint": hint})
         ws = dpo.alloc_workspace(dg, opts)
         for s in srcs:
             print("copies", opts.label(), s, flush=True)
@@ -555,14 +557,14 @@ def bench_options(workload, **over):
 @pytest.mark.slow
 def test_bfs_s22_full_size(s22):
     """The BFS headline workload at full size: the benchmarked options (also
-    with the paper's per-lane serial children and the library's default
-    replay length), the naive baseline at the same child block size, the
+    with the paper's per-lane serial children, without the claim hint and
+    with the library's default replay length), the naive baseline at the same child block size, the
     library defaults and block granularity, all 16 sources against the
     oracle, counters against the schedule counts for every source; the flat
     kernel on every fourth source."""
     g, dg, srcs = s22
     configs = [bench_options("bfs22"), bench_options("bfs22", steps_per_replay=9),
-               bench_options("bfs22", serial_wave=0),
+               bench_options("bfs22", serial_wave=0), bench_options("bfs22", claim_hint=dpo.DPO_HINT_OFF),
                dpo.Options.naive(child_block=128), dpo.Options(),
                dpo.Options(threshold=32, coarsen=8, agg=dpo.DPO_AGG_BLOCK), dpo.Options.flat()]
     wss = [dpo.alloc_workspace(dg, o) for o in configs]
@@ -571,7 +573,7 @@ def test_bfs_s22_full_size(s22):
         for j, (o, ws) in enumerate(zip(configs, wss)):
             if o.mode == dpo.DPO_MODE_FLAT and i % 4:
                 continue  # the flat kernel is slow on hubs; every fourth source
-            if j >= 4 and i % 2:
+            if j >= 5 and i % 2:
                 continue  # configurations not benchmarked: every other source
             print("bfs s22", o.label(), "K", o.steps_per_replay, int(s), flush=True)
             got, st = run_bfs(dg, int(s), o, ws=ws, stats=True)
