@@ -90,7 +90,8 @@ typedef struct {
                                many entries probes one copy of the visited state
                                and sends its atomics to a second copy; narrower
                                levels use one copy.  Affects speed only.  Default
-                               65536; 0 = always two copies.                      */
+                               65536; 0 = always two copies.  Not used by BFS
+                               with per-XCD copies (claim_hint).               */
   int32_t serial_wave;      /* 1 (default): the thresholded children of a wave's
                                parents run together, their edges 64 at a time
                                (no launch, as Sec. III-B asks, but every lane
@@ -107,19 +108,21 @@ typedef struct {
                                left (as a hardware block scheduler hands out
                                blocks), so waves whose blocks run slow do fewer.
                                Speed only.                                      */
-  int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  BFS levels
-                               with two visited copies: before its claim atomic,
-                               a lane checks and sets its vertex's bit in a
-                               bitmap private to its XCD (workgroup % 8) with
-                               plain loads and stores, so that each XCD sends at
-                               most one claim per vertex and no device-coherent
-                               load of the claimed copy is needed.  Speed only. */
+  int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  BFS: each
+                               XCD (workgroup % 8) probes a visited bitmap of its
+                               own, kept with plain loads and stores, in which a
+                               lane records a claim before sending it; the
+                               claims go to a bitmap that only atomics touch.
+                               Each XCD then sends about one claim per vertex,
+                               and no plain load reads lines the atomics are
+                               updating.  When off, a level probes one shared
+                               bitmap, or (split_min) a frozen copy while
+                               claiming in a second one.  Speed only.          */
 } dpo_options;
 
 typedef enum {
-  DPO_HINT_AUTO = 0,  /* on while the visited bitmap is at most 1 MiB (8 M
-                         vertices), so that it and the XCD's bitmap share the
-                         XCD's L2                                              */
+  DPO_HINT_AUTO = 0,  /* on for single traversals (dpo_bfs and its variants),
+                         off for launches over many queries (batch, engine)  */
   DPO_HINT_ON = 1,
   DPO_HINT_OFF = 2
 } dpo_claim_hint;

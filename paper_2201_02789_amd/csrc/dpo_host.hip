@@ -337,8 +337,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.serial_wave = o.serial_wave;
   a.dyn_pct = o.dyn_share;
   a.hint = problem == PROB_BFS &&
-           (o.claim_hint == DPO_HINT_ON ||
-            (o.claim_hint == DPO_HINT_AUTO && (uint64_t)a.vwords <= HINT_MAX_WORDS));
+           (o.claim_hint == DPO_HINT_ON || (o.claim_hint == DPO_HINT_AUTO && nq == 1));
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;

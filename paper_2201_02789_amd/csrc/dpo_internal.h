@@ -21,8 +21,7 @@ constexpr int MAX_QUERIES = 4096;  // per-query tables are staged in LDS
 constexpr int ADMIT_CHUNK = 4096;  // output slots initialised per admit workgroup
 constexpr int PRECHECK_MIN = 32;   // claim candidates per 512-lane batch above which
                                    // a coherent load precedes the atomics
-constexpr uint32_t HINT_MAX_WORDS = 1u << 18;  // BFS claim hint (auto): bitmap <= 1 MiB
-constexpr int NHINT = 8;           // claim-hint bitmaps, one per XCD
+constexpr int NHINT = 8;           // BFS per-XCD visited copies (Args::hint), one per XCD
 
 enum { PROB_BFS = 0, PROB_SSSP = 1 };
 enum { AGG_NONE = 0, AGG_WAVE = 1, AGG_BLOCK = 2, AGG_MULTI = 3, AGG_FLAT = 4 };
@@ -94,8 +93,8 @@ struct Args {
   uint32_t* grp_done;              // [3][ngroups_cap]: blocks of the group finished
   int32_t* front0;                 // [NQF * fcap + slots]
   int32_t* front1;
-  uint32_t* visit;                 // BFS: two bitmaps of vwords words, then NHINT claim
-                                   // hints; SSSP: stamps [slots]
+  uint32_t* visit;                 // BFS: two bitmaps of vwords words, then NHINT per-XCD
+                                   // copies; SSSP: stamps [slots]
   int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
   int32_t* rec_q;                  // [slots] query of each record
   int32_t* rec_slot;               // [slots] SSSP: slot of each record's parent
@@ -124,8 +123,9 @@ struct Args {
                                    // (1) or each in its parent's lane (0)
   int32_t dyn_pct;                 // child kernel: percent of each XCD group's blocks
                                    // that its waves claim in chunks (0 = even split)
-  int32_t hint;                    // BFS: per-XCD claim-hint bitmaps in use (two-copy
-                                   // levels), at visit + (2 + x) * vwords, x = XCD
+  int32_t hint;                    // BFS: per-XCD visited copies in use (probed by the
+                                   // XCD's workgroups; bitmap 0 takes the claims), at
+                                   // visit + (2 + x) * vwords, x = XCD
 };
 
 // timed: the instantiation that stamps its phases into Args::tm

@@ -208,15 +208,24 @@ struct Vis {
   uint32_t* claim;        // the level's claims / atomicMin
   uint32_t* fold;         // receives the frontier's vertices / distances
   bool split;
+  uint32_t* own;          // BFS with per-XCD copies: this XCD's copy (= probe)
 };
 
+// BFS with per-XCD copies (Args::hint): bitmap 0 receives every claim and is
+// touched by atomics only; each XCD (workgroup % 8) probes its own bitmap,
+// which holds bitmap 0 as of the level's start plus the claims this XCD has
+// sent since, kept with plain loads and stores that stay in its L2.
 template <int P>
 __device__ __forceinline__ Vis vis_of(const Args& a, uint32_t c, bool split) {
+  if (P == PROB_BFS && a.hint) {
+    uint32_t* own = a.visit + (size_t)(2u + (blockIdx.x & (NHINT - 1))) * (uint32_t)a.vwords;
+    return Vis{own, a.visit, nullptr, false, own};
+  }
   uint32_t* b0 = P == PROB_BFS ? a.visit : a.dist;
   uint32_t* b1 = P == PROB_BFS ? a.visit + a.vwords : a.dist2;
   uint32_t* pb = c ? b1 : b0;
   uint32_t* ob = c ? b0 : b1;
-  return Vis{pb, split ? ob : pb, ob, split};
+  return Vis{pb, split ? ob : pb, ob, split, nullptr};
 }
 
 __device__ __forceinline__ uint32_t coherent_load(const uint32_t* p) {
@@ -250,48 +259,37 @@ __device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const
     uint32_t word[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? pb[(uint32_t)sl[u] >> 5] : ~0u;
-    // Split level: vertices found earlier in this level are still clear in
-    // the probed bitmap, and many edges lead to each of them.  Loads of a line
-    // that device atomics are updating run several times slower than loads of
-    // a line no atomic touches, so the claimed bitmap is not read with plain
-    // loads.  With the claim hint, a candidate first tests and sets its bit in
-    // its XCD's own hint bitmap (plain loads and stores, which stay in that
-    // XCD's L2); a set bit means a lane of this XCD has sent or will send the
-    // claim, and the claim atomic decides the winner, so skipping is exact.
-    // The stores are not atomic: a lost bit only lets a second claim through.
-    // Without the hint, a batch with many candidates reads the claim words
-    // with coherent loads first; with few, that round trip would only add
-    // latency.  Either way a candidate's word is replaced by the word read,
-    // and the atomic below runs only where the bit is still clear.
+    // Per-XCD copies: a candidate first records its claim in its XCD's copy
+    // (a plain store; a set bit there means a lane of this XCD has claimed or
+    // will claim the vertex, or it was visited before the level), so each XCD
+    // sends about one claim per vertex, and no plain load ever reads the
+    // bitmap the atomics update: loads of lines that device atomics are
+    // updating run several times slower than loads of other lines.  The
+    // claim atomic alone decides the one winner, so a stale or lost bit in a
+    // copy only lets a second claim through.
+    // Two shared copies (split level): vertices found earlier in this level
+    // are still clear in the probed bitmap; a batch with many candidates reads
+    // the claim words with coherent loads first, with few that round trip
+    // would only add latency.
     bool filter = false;
-    if (vis.split) {
-      if (a.hint) {
-        filter = true;
-      } else {
-        uint32_t ncand = 0;
+    if (a.hint) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          ncand += (uint32_t)__popcll(__ballot(sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31)))));
-        filter = ncand > PRECHECK_MIN;
+      for (int u = 0; u < U; ++u) {
+        const uint32_t bit = 1u << (sl[u] & 31);
+        if (sl[u] >= 0 && !(word[u] & bit)) vis.own[(uint32_t)sl[u] >> 5] = word[u] | bit;
       }
+    } else if (vis.split) {
+      uint32_t ncand = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        ncand += (uint32_t)__popcll(__ballot(sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31)))));
+      filter = ncand > PRECHECK_MIN;
     }
     if (filter) {
-      uint32_t* hb = a.visit + (size_t)(2u + (blockIdx.x & (NHINT - 1))) * (uint32_t)a.vwords;
-      if (a.hint) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31)))) word[u] = hb[(uint32_t)sl[u] >> 5];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t bit = 1u << (sl[u] & 31);
-          if (sl[u] >= 0 && !(word[u] & bit)) hb[(uint32_t)sl[u] >> 5] = word[u] | bit;
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31))))
-            word[u] = coherent_load(&cb[(uint32_t)sl[u] >> 5]);
-      }
+      for (int u = 0; u < U; ++u)
+        if (sl[u] >= 0 && !(word[u] & (1u << (sl[u] & 31))))
+          word[u] = coherent_load(&cb[(uint32_t)sl[u] >> 5]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -579,9 +577,28 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
 
   // Fold into the copy not probed at this level: one atomic per frontier
   // entry, or, for BFS after a one-copy level or with more frontier entries
-  // than bitmap words, one per non-zero word of the probed bitmap.
-  const bool word_fold = PH != PH_SERIAL && P == PROB_BFS && split && (stale || F > (uint32_t)a.vwords);
-  const bool entry_fold = P == PROB_SSSP || (split && !word_fold);
+  // than bitmap words, one per non-zero word of the probed bitmap.  BFS with
+  // per-XCD copies: the claimed bitmap's words holding the frontier (the
+  // previous level's discoveries) are copied into every XCD's copy, word by
+  // word for a narrow frontier, else whole (each XCD's workgroups write their
+  // own copy), before pass 1 so that pass 2 mostly probes complete copies.
+  const bool own = P == PROB_BFS && a.hint;
+  const bool word_fold =
+      !own && PH != PH_SERIAL && P == PROB_BFS && split && (stale || F > (uint32_t)a.vwords);
+  const bool entry_fold = P == PROB_SSSP || (!own && split && !word_fold);
+  const bool own_words = own && PH != PH_SERIAL && F > (uint32_t)a.vwords / 8u;
+  const bool own_entries = own && PH != PH_SERIAL && !own_words;
+  if (own_words) {
+    const bool local = gridDim.x % NHINT == 0;
+    const uint32_t x0 = local ? blockIdx.x % NHINT : 0u, nx = local ? 1u : (uint32_t)NHINT;
+    const uint32_t k = local ? blockIdx.x / NHINT : blockIdx.x;
+    const uint32_t nk = local ? gridDim.x / NHINT : gridDim.x;
+    for (uint32_t w = k * PB + tid; w < (uint32_t)a.vwords; w += nk * PB) {
+      const uint32_t cw = a.visit[w];
+      if (cw)
+        for (uint32_t x = x0; x < x0 + nx; ++x) a.visit[(size_t)(2 + x) * a.vwords + w] = cw;
+    }
+  }
   // a workgroup with at most one virtual block keeps its thresholded parents
   // in registers (narrow levels are latency-bound)
   const bool in_regs = PH == PH_BOTH && nvb <= gridDim.x;
@@ -613,6 +630,9 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         else atomicMin(&vis.fold[slot], du);
       } else if (entry_fold) {
         atomicOr(&vis.fold[(uint32_t)slot >> 5], 1u << (slot & 31));
+      } else if (own_entries) {
+        const uint32_t wd = (uint32_t)slot >> 5, cw = vis.claim[wd];
+        for (uint32_t x = 0; x < (uint32_t)NHINT; ++x) a.visit[(size_t)(2 + x) * a.vwords + wd] = cw;
       }
       launch = G != AGG_FLAT && deg > 0 && deg >= p.T;
       ser = deg > 0 && !launch;
@@ -1313,8 +1333,8 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
       const uint32_t x = (i == src >> 5) ? (1u << (src & 31)) : 0u;
       a.visit[s0 / 32 + i] = x;  // both bitmaps hold the source
       a.visit[(size_t)a.vwords + s0 / 32 + i] = x;
-      if (a.hint)
-        for (uint32_t h = 0; h < (uint32_t)NHINT; ++h) a.visit[(size_t)(2 + h) * a.vwords + s0 / 32 + i] = 0u;
+      if (a.hint)  // the per-XCD copies hold the source too
+        for (uint32_t h = 0; h < (uint32_t)NHINT; ++h) a.visit[(size_t)(2 + h) * a.vwords + s0 / 32 + i] = x;
     }
   }
   if (reset) {

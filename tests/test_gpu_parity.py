@@ -198,8 +198,8 @@ def test_visited_copies_every_mode(s14p, split_min, hint):
     """Levels that probe one visited copy and update the other, levels that use
     one copy, and traversals that switch between the two from level to level
     (split_min=512 on a scale-14 graph) give the oracle's results, with the
-    workspace reused across sources; with and without the per-XCD claim hint
-    of the two-copy BFS levels."""
+    workspace reused across sources; BFS also with per-XCD visited copies
+    (claim_hint), which take the place of both."""
     g, dg = s14p
     srcs = [int(s) for s in gg.sample_sources(g, 3, 5)] + [gg.max_degree_vertex(g)]
     for base in (dpo.Options(threshold=32, coarsen=1), dpo.Options.naive(), dpo.Options.flat()):
@@ -557,7 +557,7 @@ def bench_options(workload, **over):
 @pytest.mark.slow
 def test_bfs_s22_full_size(s22):
     """The BFS headline workload at full size: the benchmarked options (also
-    with the paper's per-lane serial children, without the claim hint and
+    with the paper's per-lane serial children, without per-XCD copies and
     with the library's default replay length), the naive baseline at the same child block size, the
     library defaults and block granularity, all 16 sources against the
     oracle, counters against the schedule counts for every source; the flat

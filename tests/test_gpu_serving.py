@@ -28,13 +28,15 @@ def resident():
 
 
 @pytest.mark.parametrize("kind", ["bfs", "sssp"])
-@pytest.mark.parametrize("agg,steps,split_min,dyn", [(dpo.DPO_AGG_MULTIBLOCK, 2, 65536, 0),
-                                                     (dpo.DPO_AGG_BLOCK, 5, 65536, 0),
-                                                     (dpo.DPO_AGG_NONE, 3, 65536, 0),
-                                                     (dpo.DPO_AGG_MULTIBLOCK, 3, 0, 0),
-                                                     (dpo.DPO_AGG_MULTIBLOCK, 2, 300, 0),
-                                                     (dpo.DPO_AGG_MULTIBLOCK, 3, 65536, 25)])
-def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, split_min, dyn):
+@pytest.mark.parametrize("agg,steps,split_min,dyn,hint", [(dpo.DPO_AGG_MULTIBLOCK, 2, 65536, 0, 0),
+                                                          (dpo.DPO_AGG_BLOCK, 5, 65536, 0, 0),
+                                                          (dpo.DPO_AGG_NONE, 3, 65536, 0, 0),
+                                                          (dpo.DPO_AGG_MULTIBLOCK, 3, 0, 0, 0),
+                                                          (dpo.DPO_AGG_MULTIBLOCK, 2, 300, 0, 0),
+                                                          (dpo.DPO_AGG_MULTIBLOCK, 3, 65536, 25, 0),
+                                                          (dpo.DPO_AGG_MULTIBLOCK, 2, 65536, 0,
+                                                           dpo.DPO_HINT_ON)])
+def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, split_min, dyn, hint):
     graphs, da = resident
     rng = np.random.default_rng(11)
     reqs = []
@@ -42,9 +44,9 @@ def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, s
         g = int(rng.integers(0, len(graphs)))
         reqs.append((g, int(gg.sample_sources(graphs[g], 1, int(rng.integers(1 << 30)))[0])))
     bopts = [dpo.Options(threshold=16, coarsen=2, agg=agg, steps_per_replay=steps,
-                         split_min=split_min, dyn_share=dyn),
+                         split_min=split_min, dyn_share=dyn, claim_hint=hint),
              dpo.Options(threshold=64, coarsen=1, agg=agg, steps_per_replay=steps,
-                         split_min=split_min, dyn_share=dyn)]
+                         split_min=split_min, dyn_share=dyn, claim_hint=hint)]
     gb = [0 if g.n < 2048 else 1 for g in graphs]
     # pool of 12k slots: at most a few graphs at once, so admission waits on footprint
     eng = dpo.Engine(da, kind, bopts, graph_bucket=gb, max_queries=8, max_slots=12 * 1024)
