@@ -99,7 +99,8 @@ def agg_of(s):
 # blockDim, which the naive baseline shares) is 128 lanes on the large
 # workloads: the child kernel splits a level's blocks evenly over its waves,
 # and smaller blocks make equal block counts closer to equal edge counts.
-TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128, dyn_share=25),
+TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128, dyn_share=25,
+                       split_min=4096),
          "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),

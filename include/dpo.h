@@ -90,8 +90,9 @@ typedef struct {
                                many entries probes one copy of the visited state
                                and sends its atomics to a second copy; narrower
                                levels use one copy.  Affects speed only.  Default
-                               65536; 0 = always two copies.  Not used by BFS
-                               with per-XCD copies (claim_hint).               */
+                               65536; 0 = always two copies.  BFS with
+                               claim_hint: the levels that use the per-XCD
+                               copies.                                          */
   int32_t serial_wave;      /* 1 (default): the thresholded children of a wave's
                                parents run together, their edges 64 at a time
                                (no launch, as Sec. III-B asks, but every lane
@@ -108,16 +109,17 @@ typedef struct {
                                left (as a hardware block scheduler hands out
                                blocks), so waves whose blocks run slow do fewer.
                                Speed only.                                      */
-  int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  BFS: each
+  int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  BFS levels
+                               with at least split_min frontier entries: each
                                XCD (workgroup % 8) probes a visited bitmap of its
                                own, kept with plain loads and stores, in which a
                                lane records a claim before sending it; the
                                claims go to a bitmap that only atomics touch.
                                Each XCD then sends about one claim per vertex,
                                and no plain load reads lines the atomics are
-                               updating.  When off, a level probes one shared
-                               bitmap, or (split_min) a frozen copy while
-                               claiming in a second one.  Speed only.          */
+                               updating.  When off, such a level probes a frozen
+                               copy while claiming in a second one.  Narrower
+                               levels probe and claim one bitmap.  Speed only. */
 } dpo_options;
 
 typedef enum {

@@ -211,13 +211,15 @@ struct Vis {
   uint32_t* own;          // BFS with per-XCD copies: this XCD's copy (= probe)
 };
 
-// BFS with per-XCD copies (Args::hint): bitmap 0 receives every claim and is
-// touched by atomics only; each XCD (workgroup % 8) probes its own bitmap,
-// which holds bitmap 0 as of the level's start plus the claims this XCD has
-// sent since, kept with plain loads and stores that stay in its L2.
+// BFS with per-XCD copies (Args::hint): bitmap 0 receives every claim.  On a
+// wide level (split) it is touched by atomics only and each XCD (workgroup %
+// 8) probes its own bitmap, which holds bitmap 0 as of the level's start plus
+// the claims this XCD has sent since, kept with plain loads and stores that
+// stay in its L2; a narrow level probes and claims bitmap 0.
 template <int P>
 __device__ __forceinline__ Vis vis_of(const Args& a, uint32_t c, bool split) {
   if (P == PROB_BFS && a.hint) {
+    if (!split) return Vis{a.visit, a.visit, nullptr, false, nullptr};
     uint32_t* own = a.visit + (size_t)(2u + (blockIdx.x & (NHINT - 1))) * (uint32_t)a.vwords;
     return Vis{own, a.visit, nullptr, false, own};
   }
@@ -272,7 +274,7 @@ __device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const
     // the claim words with coherent loads first, with few that round trip
     // would only add latency.
     bool filter = false;
-    if (a.hint) {
+    if (vis.own) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t bit = 1u << (sl[u] & 31);
@@ -578,17 +580,15 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   // Fold into the copy not probed at this level: one atomic per frontier
   // entry, or, for BFS after a one-copy level or with more frontier entries
   // than bitmap words, one per non-zero word of the probed bitmap.  BFS with
-  // per-XCD copies: the claimed bitmap's words holding the frontier (the
-  // previous level's discoveries) are copied into every XCD's copy, word by
-  // word for a narrow frontier, else whole (each XCD's workgroups write their
-  // own copy), before pass 1 so that pass 2 mostly probes complete copies.
+  // per-XCD copies: a wide level starts by copying the claimed bitmap into
+  // every XCD's copy (each XCD's workgroups write their own copy), before pass
+  // 1 so that pass 2 mostly probes complete copies; narrow levels keep no
+  // copy up to date, which is why the next wide level copies it whole.
   const bool own = P == PROB_BFS && a.hint;
   const bool word_fold =
       !own && PH != PH_SERIAL && P == PROB_BFS && split && (stale || F > (uint32_t)a.vwords);
   const bool entry_fold = P == PROB_SSSP || (!own && split && !word_fold);
-  const bool own_words = own && PH != PH_SERIAL && F > (uint32_t)a.vwords / 8u;
-  const bool own_entries = own && PH != PH_SERIAL && !own_words;
-  if (own_words) {
+  if (own && split && PH != PH_SERIAL) {
     const bool local = gridDim.x % NHINT == 0;
     const uint32_t x0 = local ? blockIdx.x % NHINT : 0u, nx = local ? 1u : (uint32_t)NHINT;
     const uint32_t k = local ? blockIdx.x / NHINT : blockIdx.x;
@@ -630,9 +630,6 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
         else atomicMin(&vis.fold[slot], du);
       } else if (entry_fold) {
         atomicOr(&vis.fold[(uint32_t)slot >> 5], 1u << (slot & 31));
-      } else if (own_entries) {
-        const uint32_t wd = (uint32_t)slot >> 5, cw = vis.claim[wd];
-        for (uint32_t x = 0; x < (uint32_t)NHINT; ++x) a.visit[(size_t)(2 + x) * a.vwords + wd] = cw;
       }
       launch = G != AGG_FLAT && deg > 0 && deg >= p.T;
       ser = deg > 0 && !launch;
