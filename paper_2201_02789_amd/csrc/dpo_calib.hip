@@ -9,7 +9,7 @@
 //   a streaming int32 read with one dependent probe of a table per element
 //     (the child body: v = col[e], then visited[v]);
 //   random atomicOr on a table (the BFS claim), with and without its return;
-//   random plain stores (the level writes, the claim hints);
+//   random plain stores (the level writes, the per-XCD visited copies);
 //   random loads of a table while some workgroups update it, or a second
 //     table, with atomics (a probed bitmap that is also claimed in, against
 //     probed and claimed copies);

@@ -83,7 +83,7 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
   L.front0 = off; off = align_up(off + fslots * 4);
   L.front1 = off; off = align_up(off + fslots * 4);
-  // SSSP stamps / two BFS bitmaps and the NHINT claim hints
+  // SSSP stamps / two BFS bitmaps and the NHINT per-XCD copies
   L.visit = off; off = align_up(off + std::max((size_t)slots, (size_t)(2 + NHINT) * cdiv(slots, 32)) * 4);
   L.dist2 = off; off = align_up(off + (size_t)slots * 4);  // SSSP second distance array
   L.rec = off; off = align_up(off + (size_t)slots * 16);
