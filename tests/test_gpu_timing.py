@@ -31,7 +31,10 @@ def s16():
                                   dpo.Options(threshold=16, coarsen=1, agg=dpo.DPO_AGG_BLOCK),
                                   dpo.Options.naive(), dpo.Options.flat(),
                                   dpo.Options(threshold=512, coarsen=1, child_block=128,
-                                              split_min=262144)],
+                                              split_min=262144),
+                                  dpo.Options(threshold=64, coarsen=1, child_block=128, split_min=1024),
+                                  dpo.Options(threshold=64, coarsen=1, child_block=128, split_min=1024,
+                                              claim_hint=dpo.DPO_HINT_OFF)],
                          ids=lambda o: o.label())
 def test_timed_traversal_matches_and_rows_are_well_formed(s16, kind, opts):
     g, dg = s16

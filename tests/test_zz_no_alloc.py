@@ -35,7 +35,10 @@ def _noalloc(dg, src, opts):
 @pytest.mark.parametrize("opts", [dpo.Options(), dpo.Options(threshold=64, coarsen=1, child_block=128),
                                   dpo.Options.naive(), dpo.Options.flat(),
                                   dpo.Options(threshold=8, coarsen=2, agg=dpo.DPO_AGG_WAVE,
-                                              split_min=0, steps_per_replay=3)],
+                                              split_min=0, steps_per_replay=3),
+                                  dpo.Options(threshold=64, coarsen=1, child_block=128, split_min=1024),
+                                  dpo.Options(threshold=64, coarsen=1, child_block=128, split_min=1024,
+                                              claim_hint=dpo.DPO_HINT_OFF)],
                          ids=lambda o: o.label())
 def test_noalloc_matches_workspace_call_then_smaller_input(opts):
     big = gg.rmat(16, 16, 16, perm_seed=24)      # 65,536 vertices
