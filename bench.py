@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--child-block", type=int, default=None, choices=[64, 128, 256])
     p.add_argument("--dyn-share", type=int, default=None,
                    help="percent of the child blocks claimed in chunks (0 = even split)")
+    p.add_argument("--claim-hint", type=int, default=None, choices=[0, 1, 2],
+                   help="BFS per-XCD visited copies: 0 auto, 1 on, 2 off (also for the serving engines)")
     p.add_argument("--breakdown", action="store_true",
                    help="execution-time breakdown (Sec. VIII-B) of bfs22 or sssp21 at CF 1..8")
     p.add_argument("--sweep", action="store_true",
@@ -750,6 +752,8 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
         tuned["dyn_share"] = args.dyn_share
     if overrides and args.child_block is not None:
         tuned["child_block"] = args.child_block
+    if overrides and args.claim_hint is not None:
+        tuned["claim_hint"] = args.claim_hint
     a = agg_of(args.agg) if overrides else None
     if a:
         tuned["agg"], tuned["agg_blocks"] = a
@@ -1143,8 +1147,8 @@ def bench_serve(args, dpo, torch, full_line=False):
     def opts(kind):
         T = args.threshold if args.threshold is not None else SERVE_T[kind]
         return [dpo.Options(threshold=T, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
-                            steps_per_replay=4, child_block=128,
-                            dyn_share=SERVE_DYN[kind])]
+                            steps_per_replay=4, child_block=128, dyn_share=SERVE_DYN[kind],
+                            claim_hint=args.claim_hint or 0)]
     s_bfs, s_sssp = torch.cuda.Stream(), torch.cuda.Stream()
     max_slots = 1 << 24
     engines = {"bfs": dpo.Engine(da, "bfs", opts("bfs"), max_queries=256, max_slots=max_slots,

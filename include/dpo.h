@@ -123,8 +123,8 @@ typedef struct {
 } dpo_options;
 
 typedef enum {
-  DPO_HINT_AUTO = 0,  /* on for single traversals (dpo_bfs and its variants),
-                         off for launches over many queries (batch, engine)  */
+  DPO_HINT_AUTO = 0,  /* on for single traversals (dpo_bfs and its variants)
+                         and the serving engine, off for dpo_bfs_batch         */
   DPO_HINT_ON = 1,
   DPO_HINT_OFF = 2
 } dpo_claim_hint;

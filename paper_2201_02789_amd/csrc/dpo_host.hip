@@ -291,7 +291,7 @@ struct SetRun {
 dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_options& o,
                        int64_t slots, int32_t nq, void* out, void* ws, size_t ws_bytes,
                        void* stream, bool count_stats, SetRun* sr,
-                       unsigned long long* tm = nullptr) {
+                       unsigned long long* tm = nullptr, bool batch_call = false) {
   if (slots < 1 || slots > INT32_MAX || nq < 1 || nq > MAX_QUERIES) return DPO_ERR_ARG;
   const Layout lay = layout_for(slots, nq, o);
   if (ws_bytes < lay.total) return DPO_ERR_WORKSPACE;
@@ -337,7 +337,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.serial_wave = o.serial_wave;
   a.dyn_pct = o.dyn_share;
   a.hint = problem == PROB_BFS &&
-           (o.claim_hint == DPO_HINT_ON || (o.claim_hint == DPO_HINT_AUTO && nq == 1));
+           (o.claim_hint == DPO_HINT_ON || (o.claim_hint == DPO_HINT_AUTO && !batch_call));
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
@@ -554,7 +554,7 @@ dpo_status traverse_batch(int problem, const dpo_arena* ar, const dpo_query* qs,
   if (s != DPO_OK) return s;
   SetRun sr;
   s = prepare_set(r, problem, &ar->csr, bopts[0], slots, nq, out, ws, ws_bytes, stream,
-                  st != nullptr, &sr);
+                  st != nullptr, &sr, nullptr, /*batch_call=*/true);
   if (s != DPO_OK) return s;
   Query* hq = r.host_q;
   int64_t slot = 0;

@@ -34,8 +34,8 @@ def resident():
                                                           (dpo.DPO_AGG_MULTIBLOCK, 3, 0, 0, 0),
                                                           (dpo.DPO_AGG_MULTIBLOCK, 2, 300, 0, 0),
                                                           (dpo.DPO_AGG_MULTIBLOCK, 3, 65536, 25, 0),
-                                                          (dpo.DPO_AGG_MULTIBLOCK, 2, 65536, 0,
-                                                           dpo.DPO_HINT_ON)])
+                                                          (dpo.DPO_AGG_MULTIBLOCK, 2, 1024, 0,
+                                                           dpo.DPO_HINT_OFF)])
 def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, split_min, dyn, hint):
     graphs, da = resident
     rng = np.random.default_rng(11)
