@@ -162,7 +162,8 @@ void dpo_default_options(dpo_options* o);
  * vertex for large graphs.  0 on bad args.
  * Layout, all inside the caller's buffer: traversal state and counters, two
  * frontier buffers (64 sharded queues plus an overflow queue), a per-vertex
- * visit word (two visited bitmaps for BFS, iteration stamps for SSSP), a
+ * visit word (for BFS two visited bitmaps and one per XCD, for SSSP iteration
+ * stamps), a
  * second distance array (SSSP), launch records of 24 bytes per vertex, a list
  * of thresholded parents of 16 bytes per vertex, 8 descriptor queues of 16
  * bytes per possible aggregated grid and per-workgroup counters. */
