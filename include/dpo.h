@@ -154,7 +154,9 @@ typedef struct {
 } dpo_stats;
 
 /* Fills *o with the defaults: nested, T = 128, CF = 8, 4-block aggregation,
- * child block 256, 16 steps per replay, no aggregation threshold. */
+ * child block 256, 16 steps per replay, no aggregation threshold, two visited
+ * copies from 65,536 frontier entries, wave-run thresholded children, even
+ * child shares, claim_hint automatic. */
 void dpo_default_options(dpo_options* o);
 
 /* Device workspace bytes needed by dpo_bfs / dpo_sssp on a graph with g->n
@@ -163,8 +165,8 @@ void dpo_default_options(dpo_options* o);
  * Layout, all inside the caller's buffer: traversal state and counters, two
  * frontier buffers (64 sharded queues plus an overflow queue), a per-vertex
  * visit word (for BFS two visited bitmaps and one per XCD, for SSSP iteration
- * stamps), a
- * second distance array (SSSP), launch records of 24 bytes per vertex, a list
+ * stamps), a second distance array (SSSP), launch records of 24 bytes per
+ * vertex, a list
  * of thresholded parents of 16 bytes per vertex, 8 descriptor queues of 16
  * bytes per possible aggregated grid and per-workgroup counters. */
 size_t dpo_workspace_bytes(const dpo_csr* g, const dpo_options* o);
