@@ -44,7 +44,9 @@
 // L2-resident), claims v in a second bitmap and writes its level; SSSP relaxes
 // a second distance array with atomicMin and queues v once per iteration
 // through an iteration stamp.  The probed and the updated copies swap every
-// level.
+// level.  BFS single traversals and the serving engine instead give each XCD a
+// probed copy of its own on wide levels and claim in one bitmap that only
+// atomics touch (Vis, vis_of).
 //
 // Queries: a launch may carry many traversals ("queries") over graphs packed
 // in one CSR arena.  Query q owns the output slots [slot0, slot0 + n) (slot0 a
