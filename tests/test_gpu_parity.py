@@ -512,9 +512,14 @@ def test_structured_graphs(name, make, src):
     dg = dpo.DeviceGraph.from_host(g)
     want, _ = oracle.bfs(g, src)
     dwant = oracle.dijkstra(g, src)
+    # the last two: per-XCD visited copies on every level, and two shared
+    # copies on every level, on odd sizes, isolated vertices and deep or
+    # one-level-wide shapes
     for opts in (dpo.Options(), dpo.Options.flat(), dpo.Options.naive(),
                  dpo.Options(threshold=0, coarsen=16, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=16),
-                 dpo.Options(threshold=4, coarsen=2, agg=dpo.DPO_AGG_WAVE, steps_per_replay=3)):
+                 dpo.Options(threshold=4, coarsen=2, agg=dpo.DPO_AGG_WAVE, steps_per_replay=3),
+                 dpo.Options(threshold=8, coarsen=1, split_min=0, claim_hint=dpo.DPO_HINT_ON),
+                 dpo.Options(threshold=8, coarsen=1, split_min=0, claim_hint=dpo.DPO_HINT_OFF)):
         print(name, opts.label(), flush=True)
         got, st = run_bfs(dg, src, opts)
         assert np.array_equal(got, want), (name, opts.label())
