@@ -5,7 +5,7 @@ Sec. VIII-C of the paper reports that the best threshold is usually the one
 that leaves about 6,000-8,000 child-grid launches, that performance is not
 sensitive to the coarsening factor once it is large enough, that warp
 granularity is never the best, and that a handful of runs finds a point close
-to the best.  The tuner follows that in two stages:
+to the best.  The tuner follows that in three stages:
 
 1. per size bucket, threshold and coarsening: start from the threshold whose
    launch count (parents of degree >= T, summed over the bucket's queries) is
@@ -14,7 +14,9 @@ to the best.  The tuner follows that in two stages:
    neighbour is faster or after `max_runs` timed points;
 2. aggregation granularity, for the whole launch: block, 4-block, 16-block
    and grid (wave is skipped, as the paper finds it never best), timing the
-   whole batch with every bucket at its stage-1 point;
+   whole batch with every bucket at its stage-1 point, then the other
+   original child block sizes (64, 128, 256 lanes) at the fastest
+   granularity;
 3. a check on the whole batch: each bucket in turn goes back to the base
    (T, CF) and keeps it when the whole batch is faster that way (a bucket's
    best point timed alone need not be best beside the others, and stage-1
@@ -22,14 +24,15 @@ to the best.  The tuner follows that in two stages:
 
 Granularity is a property of the launch, not of a bucket: the parent
 workgroups' frontier entries mix queries of every bucket, and aggregation
-groups are formed over those entries.  The result can be saved as JSON and
+groups are formed over those entries; so is the child block size, which fixes
+the child kernel's slice arithmetic.  The result can be saved as JSON and
 reloaded, so a tuned table is reused across runs.
 """
 from __future__ import annotations
 
 import json
 import time
-from dataclasses import asdict
+from dataclasses import asdict, replace
 
 import numpy as np
 
@@ -58,6 +61,7 @@ def heuristic_threshold(graphs, queries) -> int:
     return min(T_GRID, key=lambda T: abs(np.log((counts[T] + 1) / target)))
 
 
+CHILD_BLOCKS = (64, 128, 256)
 GRANULARITIES = ((dpo.DPO_AGG_BLOCK, 4, "block"), (dpo.DPO_AGG_MULTIBLOCK, 4, "4-block"),
                  (dpo.DPO_AGG_MULTIBLOCK, 16, "16-block"), (dpo.DPO_AGG_GRID, 4, "grid"))
 
@@ -98,6 +102,17 @@ def tune_granularity(kind, arena, queries, bucket_opts, log=None, reps=3):
         trace.append((name, t, cand))
         if log:
             log(f"[tune] {kind} granularity {name}: {t * 1e3:.3f} ms")
+    name, t, best = min(trace, key=lambda x: x[1])
+    # the original child block size at that granularity (also per launch: it
+    # fixes the child kernel's slice arithmetic)
+    for cb in CHILD_BLOCKS:
+        if cb == best[0].child_block:
+            continue
+        cand = [replace(o, child_block=cb) for o in best]
+        tc = _time_batch(kind, arena, queries, cand, reps)
+        trace.append((f"{name}-CB{cb}", tc, cand))
+        if log:
+            log(f"[tune] {kind} granularity {name}, child block {cb}: {tc * 1e3:.3f} ms")
     name, t, best = min(trace, key=lambda x: x[1])
     return best, [(n, v) for n, v, _ in trace]
 

@@ -31,16 +31,19 @@ def test_greedy_walk_and_granularity_stage(monkeypatch):
         calls.append((len(qs), o.label()))
         cost = abs(autotune.T_GRID.index(o.threshold) - 3) + abs(autotune.CF_GRID.index(o.coarsen) - 1)
         gran = {dpo.DPO_AGG_BLOCK: 3, dpo.DPO_AGG_GRID: 2}.get(o.agg, 1 if o.agg_blocks == 16 else 1.5)
-        return cost + gran
+        cb = {64: -0.25, 128: 0.0, 256: 0.5}[o.child_block]
+        return cost + gran + cb
 
     monkeypatch.setattr(autotune, "_time_batch", fake_time)
     base = dpo.Options(threshold=32, coarsen=1, child_block=128)
     opts, traces, gtrace = autotune.tune("bfs", None, graphs, queries, [0, 0], 1, base, max_runs=20)
     assert (opts[0].threshold, opts[0].coarsen) == (128, 2)
     assert (opts[0].agg, opts[0].agg_blocks) == (dpo.DPO_AGG_MULTIBLOCK, 16)
-    assert opts[0].child_block == 128
-    assert [n for n, _ in gtrace][:4] == ["block", "4-block", "16-block", "grid"]
-    assert gtrace[4][0] == "tuned" and gtrace[5][0] == "bucket0-base"
+    # the child block stage runs at the fastest granularity and keeps the fastest size
+    assert opts[0].child_block == 64
+    assert [n for n, _ in gtrace][:6] == ["block", "4-block", "16-block", "grid", "16-block-CB64",
+                                          "16-block-CB256"]
+    assert gtrace[6][0] == "tuned" and gtrace[7][0] == "bucket0-base"
     assert len(traces) == 1 and len(traces[0]) <= 20
     # a bucket without queries keeps the base point
     opts2, traces2, _ = autotune.tune("bfs", None, graphs, queries, [0, 0], 2, base, max_runs=4)
