@@ -112,6 +112,7 @@ TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block
 
 SERVE_T = {"bfs": 64, "sssp": 256}  # thresholds of the serving engines
 SERVE_DYN = {"bfs": 0, "sssp": 50}  # percent of child blocks claimed in chunks
+SERVE_CB = {"bfs": 128, "sssp": 128}  # original child block sizes of the serving engines
 
 
 class Workload:
@@ -1147,7 +1148,7 @@ def bench_serve(args, dpo, torch, full_line=False):
     def opts(kind):
         T = args.threshold if args.threshold is not None else SERVE_T[kind]
         return [dpo.Options(threshold=T, coarsen=1, agg=dpo.DPO_AGG_MULTIBLOCK, agg_blocks=4,
-                            steps_per_replay=4, child_block=128, dyn_share=SERVE_DYN[kind],
+                            steps_per_replay=4, child_block=SERVE_CB[kind], dyn_share=SERVE_DYN[kind],
                             claim_hint=args.claim_hint or 0)]
     s_bfs, s_sssp = torch.cuda.Stream(), torch.cuda.Stream()
     max_slots = 1 << 24
