@@ -35,6 +35,10 @@ struct Layout {
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t round32(int64_t x) { return (x + 31) & ~(int64_t)31; }
 
+// BFS: byte offset of the found bytes in the visit region, after the two
+// bitmaps and the per-XCD copies
+size_t found_offset(int64_t slots) { return align_up((size_t)(2 + NHINT) * cdiv(slots, 32) * 4); }
+
 int gran_of(const dpo_options& o) {
   if (o.mode == DPO_MODE_FLAT) return AGG_FLAT;
   switch (o.agg) {
@@ -83,8 +87,8 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
   L.front0 = off; off = align_up(off + fslots * 4);
   L.front1 = off; off = align_up(off + fslots * 4);
-  // SSSP stamps / two BFS bitmaps and the NHINT per-XCD copies
-  L.visit = off; off = align_up(off + std::max((size_t)slots, (size_t)(2 + NHINT) * cdiv(slots, 32)) * 4);
+  // SSSP stamps / two BFS bitmaps, the NHINT per-XCD copies and the found bytes
+  L.visit = off; off = align_up(off + std::max((size_t)slots * 4, found_offset(slots) + (size_t)cdiv(slots, 32) * 32));
   L.dist2 = off; off = align_up(off + (size_t)slots * 4);  // SSSP second distance array
   L.rec = off; off = align_up(off + (size_t)slots * 16);
   L.rec_q = off; off = align_up(off + (size_t)slots * 4);
@@ -124,7 +128,7 @@ dpo_status check_graph(const dpo_csr* g, bool need_w) {
 struct CachedGraph {
   const void* parent;
   const void* child;
-  const void* serial;
+  const void* third;
   int pgrid, cgrid, steps;
   Args args;
   hipGraphExec_t exec;
@@ -218,15 +222,15 @@ dpo_status add_node(hipGraph_t graph, hipGraphNode_t* prev, const void* fn, int 
   return DPO_OK;
 }
 
-// K level steps (parent kernel, then child kernel unless flat, then the
-// thresholded children's kernel if any, on the parent kernel's grid) and the
-// advance of the level base, as one instantiated graph.
-dpo_status get_exec(Runtime& r, const void* parent, const void* child, const void* serial,
+// K level steps (parent kernel, then child kernel unless flat, then the third
+// kernel if any, on the parent kernel's grid: SSSP's thresholded children or
+// BFS's harvest) and the advance of the level base, as one instantiated graph.
+dpo_status get_exec(Runtime& r, const void* parent, const void* child, const void* third,
                     int pgrid, int cgrid, int steps, const Args& args, hipGraphExec_t* out,
                     bool cached = true) {
   for (auto& e : r.graphs) {
     if (!cached) break;
-    if (e.parent == parent && e.child == child && e.serial == serial && e.pgrid == pgrid &&
+    if (e.parent == parent && e.child == child && e.third == third && e.pgrid == pgrid &&
         e.cgrid == cgrid &&
         e.steps == steps && std::memcmp(&e.args, &args, sizeof(Args)) == 0) {
       e.last_use = ++r.tick;
@@ -245,7 +249,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, const voi
     void* params[] = {&a, &step_ids[i]};
     s = add_node(graph, &prev, parent, pgrid, PB, params);
     if (s == DPO_OK && child) s = add_node(graph, &prev, child, cgrid, PB, params);
-    if (s == DPO_OK && serial) s = add_node(graph, &prev, serial, pgrid, PB, params);
+    if (s == DPO_OK && third) s = add_node(graph, &prev, third, pgrid, PB, params);
   }
   State* st = a.st;
   uint32_t k = (uint32_t)steps;
@@ -267,7 +271,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, const voi
     (void)hipGraphExecDestroy(r.graphs[victim].exec);
     r.graphs.erase(r.graphs.begin() + victim);
   }
-  r.graphs.push_back(CachedGraph{parent, child, serial, pgrid, cgrid, steps, args, exec, ++r.tick});
+  r.graphs.push_back(CachedGraph{parent, child, third, pgrid, cgrid, steps, args, exec, ++r.tick});
   *out = exec;
   return DPO_OK;
 }
@@ -280,7 +284,9 @@ struct SetRun {
   Args a{};
   const void* parent = nullptr;
   const void* child = nullptr;
-  const void* serial = nullptr;  // thresholded children after the child kernel
+  // after the child kernel: SSSP's thresholded children, or BFS's harvest
+  // (per-XCD copies)
+  const void* third = nullptr;
   int pgrid = 0, cgrid = 0, steps = kDefaultSteps;
   hipStream_t stream = nullptr;
   int32_t* qlist = nullptr;  // device: indices of the queries being admitted
@@ -300,7 +306,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   sr->lay = lay;
   sr->parent = parent_kernel_ptr(problem, gran);
   sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem);
-  sr->serial = serial_kernel_ptr(problem, gran);
+  sr->third = serial_kernel_ptr(problem, gran);
   if (!sr->parent) return DPO_ERR_UNSUPPORTED;
   char* base = (char*)ws;
   Args& a = sr->a;
@@ -317,6 +323,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.front0 = (int32_t*)(base + lay.front0);
   a.front1 = (int32_t*)(base + lay.front1);
   a.visit = (uint32_t*)(base + lay.visit);
+  a.found = problem == PROB_BFS ? (uint8_t*)(base + lay.visit + found_offset(slots)) : nullptr;
   a.dist2 = problem == PROB_SSSP ? (uint32_t*)(base + lay.dist2) : nullptr;
   a.vwords = (int32_t)cdiv(slots, 32);
   a.rec = (int4*)(base + lay.rec);
@@ -338,6 +345,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.dyn_pct = o.dyn_share;
   a.hint = problem == PROB_BFS &&
            (o.claim_hint == DPO_HINT_ON || (o.claim_hint == DPO_HINT_AUTO && !batch_call));
+  if (a.hint) sr->third = harvest_kernel_ptr();
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
@@ -345,20 +353,21 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   sr->qlist = (int32_t*)(base + lay.qlist);
   sr->pgrid = persistent_grid(r, sr->parent);
   // the thresholded children's kernel walks the lists of the parent kernel's
-  // workgroups: one grid for both, all of it resident in either
-  if (sr->serial) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->serial));
+  // workgroups: one grid for both, all of it resident in either (the harvest
+  // runs on any grid)
+  if (sr->third && !a.hint) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
   sr->cgrid = sr->child ? persistent_grid(r, sr->child) : 0;
   sr->steps = o.steps_per_replay ? o.steps_per_replay : kDefaultSteps;
   sr->stream = (hipStream_t)stream;
   if (tm) {
     sr->parent = parent_kernel_ptr(problem, gran, true);
     sr->child = sr->child ? child_kernel_ptr(problem, true) : nullptr;
-    sr->serial = serial_kernel_ptr(problem, gran, true);
+    sr->third = a.hint ? harvest_kernel_ptr(true) : serial_kernel_ptr(problem, gran, true);
     // a timed kernel that needs more registers than its product one runs on
     // the grid that is resident at its own occupancy (a larger grid would run
     // in two rounds and time the second round's wait as work)
     sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->parent));
-    if (sr->serial) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->serial));
+    if (sr->third) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
     if (sr->child) sr->cgrid = std::min(sr->cgrid, persistent_grid(r, sr->child));
     a.tm = tm;
   }
@@ -445,7 +454,7 @@ dpo_status replay(Runtime& r, SetRun& sr, hipGraphExec_t exec) {
 dpo_status run_to_completion(Runtime& r, SetRun& sr, int64_t max_levels) {
   hipGraphExec_t exec;
   dpo_status s =
-      get_exec(r, sr.parent, sr.child, sr.serial, sr.pgrid, sr.cgrid, sr.steps, sr.a, &exec);
+      get_exec(r, sr.parent, sr.child, sr.third, sr.pgrid, sr.cgrid, sr.steps, sr.a, &exec);
   if (s != DPO_OK) return s;
   const int64_t max_replays = max_levels / sr.steps + 2;
   for (int64_t rep = 0; rep < max_replays; ++rep) {
@@ -607,8 +616,8 @@ dpo_status launch_step(SetRun& sr, uint32_t step) {
   if (sr.child &&
       hipLaunchKernel(sr.child, dim3((unsigned)sr.cgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
-  if (sr.serial &&
-      hipLaunchKernel(sr.serial, dim3((unsigned)sr.pgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
+  if (sr.third &&
+      hipLaunchKernel(sr.third, dim3((unsigned)sr.pgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
   return DPO_OK;
 }
@@ -870,10 +879,17 @@ dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_opt
     e->hq = (Query*)((char*)p + 64);
     e->hlist = (int32_t*)(e->hq + max_queries);
     std::memset(e->hq, 0, (size_t)max_queries * sizeof(Query));
-    s = get_exec(r, e->sr.parent, e->sr.child, e->sr.serial, e->sr.pgrid, e->sr.cgrid,
+    s = get_exec(r, e->sr.parent, e->sr.child, e->sr.third, e->sr.pgrid, e->sr.cgrid,
                  e->sr.steps, e->sr.a, &e->exec, false);
   }
   if (s == DPO_OK) s = start_set(r, e->sr);
+  if (s == DPO_OK && e->sr.a.hint) {
+    // no query has been admitted to any slot yet: no found vertex anywhere
+    void* cp[] = {&e->sr.a};
+    if (hipLaunchKernel(clear_found_kernel_ptr(), dim3(init_grid(r, max_slots / 4)), dim3(PB), cp,
+                        0, e->sr.stream) != hipSuccess)
+      s = DPO_ERR_HIP;
+  }
   if (s == DPO_OK &&
       hipMemcpyAsync(e->sr.a.q, e->hq, (size_t)max_queries * sizeof(Query), hipMemcpyHostToDevice,
                      e->sr.stream) != hipSuccess)

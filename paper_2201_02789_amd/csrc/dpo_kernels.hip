@@ -45,8 +45,9 @@
 // a second distance array with atomicMin and queues v once per iteration
 // through an iteration stamp.  The probed and the updated copies swap every
 // level.  BFS single traversals and the serving engine instead give each XCD a
-// probed copy of its own on wide levels and claim in one bitmap that only
-// atomics touch (Vis, vis_of).
+// probed copy of its own on wide levels and record discoveries as bytes, which
+// a third kernel, the harvest, turns into levels and the next frontier (Vis,
+// vis_of, harvest_kernel).
 //
 // Queries: a launch may carry many traversals ("queries") over graphs packed
 // in one CSR arena.  Query q owns the output slots [slot0, slot0 + n) (slot0 a
@@ -213,11 +214,12 @@ struct Vis {
   uint32_t* own;          // BFS with per-XCD copies: this XCD's copy (= probe)
 };
 
-// BFS with per-XCD copies (Args::hint): bitmap 0 receives every claim.  On a
-// wide level (split) it is touched by atomics only and each XCD (workgroup %
-// 8) probes its own bitmap, which holds bitmap 0 as of the level's start plus
-// the claims this XCD has sent since, kept with plain loads and stores that
-// stay in its L2; a narrow level probes and claims bitmap 0.
+// BFS with per-XCD copies (Args::hint): bitmap 0 is the visited set.  On a
+// wide level (split) it does not change until the harvest kernel, and each XCD
+// (workgroup % 8) probes its own bitmap, which holds bitmap 0 as of the
+// level's start plus the vertices this XCD has found since, kept with plain
+// loads and stores that stay in its L2; a narrow level probes and claims
+// bitmap 0 with atomics and appends in place.
 template <int P>
 __device__ __forceinline__ Vis vis_of(const Args& a, uint32_t c, bool split) {
   if (P == PROB_BFS && a.hint) {
@@ -263,26 +265,31 @@ __device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const
     uint32_t word[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) word[u] = sl[u] >= 0 ? pb[(uint32_t)sl[u] >> 5] : ~0u;
-    // Per-XCD copies: a candidate first records its claim in its XCD's copy
-    // (a plain store; a set bit there means a lane of this XCD has claimed or
-    // will claim the vertex, or it was visited before the level), so each XCD
-    // sends about one claim per vertex, and no plain load ever reads the
-    // bitmap the atomics update: loads of lines that device atomics are
-    // updating run several times slower than loads of other lines.  The
-    // claim atomic alone decides the one winner, so a stale or lost bit in a
-    // copy only lets a second claim through.
+    // Per-XCD copies (wide level): a candidate records itself in its XCD's
+    // copy and in the found bytes, both plain stores, and nothing else: no
+    // atomic, no level, no append.  The harvest kernel after the level takes
+    // every found vertex that bitmap 0 (visited before the level) lacks, so
+    // the level's discoveries cost no device atomics, which the chip runs at
+    // a few tens of G/s for random addresses.  A set bit in the copy means a
+    // lane of this XCD found the vertex at this level, or it was visited
+    // before; a stale or lost bit only lets a second found store through.
+    if (vis.own) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t bit = 1u << (sl[u] & 31);
+        if (sl[u] >= 0 && !(word[u] & bit)) {
+          vis.own[(uint32_t)sl[u] >> 5] = word[u] | bit;
+          a.found[sl[u]] = 1;
+        }
+      }
+      return;
+    }
     // Two shared copies (split level): vertices found earlier in this level
     // are still clear in the probed bitmap; a batch with many candidates reads
     // the claim words with coherent loads first, with few that round trip
     // would only add latency.
     bool filter = false;
-    if (vis.own) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t bit = 1u << (sl[u] & 31);
-        if (sl[u] >= 0 && !(word[u] & bit)) vis.own[(uint32_t)sl[u] >> 5] = word[u] | bit;
-      }
-    } else if (vis.split) {
+    if (vis.split) {
       uint32_t ncand = 0;
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -582,10 +589,10 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
   // Fold into the copy not probed at this level: one atomic per frontier
   // entry, or, for BFS after a one-copy level or with more frontier entries
   // than bitmap words, one per non-zero word of the probed bitmap.  BFS with
-  // per-XCD copies: a wide level starts by copying the claimed bitmap into
-  // every XCD's copy (each XCD's workgroups write their own copy), before pass
-  // 1 so that pass 2 mostly probes complete copies; narrow levels keep no
-  // copy up to date, which is why the next wide level copies it whole.
+  // per-XCD copies: a wide level starts by copying bitmap 0 into every XCD's
+  // copy (each XCD's workgroups write their own copy), before pass 1 so that
+  // pass 2 mostly probes complete copies; narrow levels keep no copy up to
+  // date, which is why the next wide level copies it whole.
   const bool own = P == PROB_BFS && a.hint;
   const bool word_fold =
       !own && PH != PH_SERIAL && P == PROB_BFS && split && (stale || F > (uint32_t)a.vwords);
@@ -1276,6 +1283,60 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   tm_write<TM>(a, pc, TK_CHILD, L, t_entry, tid);
 }
 
+// ------------------------------------------------------------ harvest kernel
+// BFS with per-XCD copies, after a wide level's child kernel: a found vertex
+// that bitmap 0 lacks was discovered at this level.  It gets its level, its
+// bit in bitmap 0 and a place in the next frontier (in slot order, which also
+// makes the next level's row loads mostly consecutive).  One lane per slot: a
+// wave reads 64 found bytes and the two bitmap words they map to, and owns
+// those words for the kernel.  Found bytes are never cleared within a
+// traversal: one set at an earlier level belongs to a vertex that the harvest
+// of that level put into bitmap 0.  Admission clears a query's found bytes,
+// and a serving engine clears all of them when it is created
+// (clear_found_kernel), so slots outside every admitted query hold none.  A
+// narrow level claimed and appended in place, and its harvest returns at once.
+template <bool TM>
+__global__ __launch_bounds__(PB) void harvest_kernel(Args a, uint32_t step) {
+  __shared__ int32_t s_stage[NW][STAGE];
+  __shared__ uint32_t s_bc[NW + 8];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  State* st = a.st;
+  uint64_t t_entry = 0;
+  if (TM) t_entry = realtime();
+  PhaseClock<TM> pc;
+  pc.start();
+  if (st->done || st->error) return;
+  const uint32_t L = st->base + step;
+  LevelSet* cur = &st->set[L % 3];
+  if (!(cur->vmode & 2u)) return;
+  int32_t* fout = (L & 1) ? a.front0 : a.front1;
+  Stage s{s_stage[wave], 0u};
+  const uint32_t n = (uint32_t)a.slots;
+  for (uint32_t b = (blockIdx.x * NW + wave) * 64u; b < n; b += gridDim.x * PB) {
+    const uint32_t v = b + (uint32_t)lane;
+    uint32_t c = 0;
+    bool nw = false;
+    if (v < n) {
+      c = a.visit[v >> 5];
+      nw = a.found[v] != 0 && !((c >> (v & 31)) & 1u);
+    }
+    const unsigned long long m = __ballot(nw);
+    if (m) {  // wave-uniform
+      if (nw) a.level[v] = (int32_t)(L + 1) - a.q[a.qmap[v >> 5]].lstart;
+      // lanes 0 and 32 own the words of slots b .. b + 31 and b + 32 .. b + 63
+      if ((lane & 31) == 0) {
+        const uint32_t bits = (uint32_t)(m >> (lane & 32));
+        if (bits) a.visit[v >> 5] = c | bits;
+      }
+    }
+    stage_push(s, nw, (int32_t)v, a, cur, fout, lane);
+  }
+  block_flush(s, a, cur, fout, tid, s_bc);
+  pc.mark(TP_CHILD);
+  tm_write<TM>(a, pc, TK_HARVEST, L, t_entry, tid);
+}
+
 // ------------------------------------------------------------ init / admit / advance
 // Traversal-set start: level sets and counters cleared.  Queries are
 // started by admit_kernel.
@@ -1332,8 +1393,11 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
       const uint32_t x = (i == src >> 5) ? (1u << (src & 31)) : 0u;
       a.visit[s0 / 32 + i] = x;  // both bitmaps hold the source
       a.visit[(size_t)a.vwords + s0 / 32 + i] = x;
-      if (a.hint)  // the per-XCD copies hold the source too
+      if (a.hint) {  // the per-XCD copies hold the source too; nothing found yet
         for (uint32_t h = 0; h < (uint32_t)NHINT; ++h) a.visit[(size_t)(2 + h) * a.vwords + s0 / 32 + i] = x;
+        uint32_t* f = (uint32_t*)(a.found + (size_t)(s0 / 32 + i) * 32);
+        for (int k = 0; k < 8; ++k) f[k] = 0u;
+      }
     }
   }
   if (reset) {
@@ -1346,6 +1410,15 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
       a.grp_done[i] = 0;
     }
   }
+}
+
+// BFS with per-XCD copies: every found byte of the workspace cleared (a
+// serving engine's output arena has slots that no query has been admitted to
+// yet; the harvest kernel must see no found vertex there).
+__global__ __launch_bounds__(PB) void clear_found_kernel(Args a) {
+  uint32_t* f = (uint32_t*)a.found;
+  const uint32_t nw = (uint32_t)a.vwords * 8u;
+  for (uint32_t i = blockIdx.x * PB + threadIdx.x; i < nw; i += gridDim.x * PB) f[i] = 0u;
 }
 
 // Second half of admission (after admit_kernel): sources into frontier L.
@@ -1403,6 +1476,10 @@ const void* serial_kernel_ptr(int problem, int gran, bool timed) {
                : parent_for<PROB_SSSP, PH_SERIAL, false>(gran);
 }
 
+const void* harvest_kernel_ptr(bool timed) {
+  return timed ? (const void*)harvest_kernel<true> : (const void*)harvest_kernel<false>;
+}
+
 const void* child_kernel_ptr(int problem, bool timed) {
   if (timed)
     return problem == PROB_BFS ? (const void*)child_kernel<PROB_BFS, true>
@@ -1419,6 +1496,8 @@ const void* admit_kernel_ptr(int problem) {
 }
 
 const void* admit_sources_kernel_ptr() { return (const void*)admit_sources_kernel; }
+
+const void* clear_found_kernel_ptr() { return (const void*)clear_found_kernel; }
 
 const void* advance_kernel_ptr() { return (const void*)advance_kernel; }
 
