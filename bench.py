@@ -103,7 +103,7 @@ def agg_of(s):
 # and smaller blocks make equal block counts closer to equal edge counts.
 TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128, dyn_share=25,
                        split_min=4096),
-         "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4, child_block=128),
+         "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4, child_block=128, split_min=4096),
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=512, coarsen=1, agg=3, agg_blocks=4, split_min=262144,
@@ -245,6 +245,9 @@ def reached_stats(dpo, torch, wl, dg, opts):
     return res, passed
 
 
+# the kernels of a level step (SSSP runs parent_kernel twice; BFS single
+# traversals add the harvest)
+LEVEL_KERNELS = ("parent_kernel", "child_kernel", "harvest_kernel")
 KERNEL_SOURCES = ["paper_2201_02789_amd/csrc/dpo_kernels.hip",
                   "paper_2201_02789_amd/csrc/dpo_host.hip",
                   "paper_2201_02789_amd/csrc/dpo_internal.h"]
@@ -562,7 +565,7 @@ def summarize_counters(args, d):
             n = _short(r["Kernel_Name"])
             if n == "init_kernel":
                 inits += 1
-            if n.startswith(("parent_kernel", "child_kernel")):
+            if n.startswith(LEVEL_KERNELS):
                 c = agg.setdefault(n, {})
                 c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
         trav[i] = inits / ncnt  # one row per counter per dispatch
@@ -608,7 +611,7 @@ def summarize_profiles(args, d):
     with open(os.path.join(d, "trace", "out.json")) as f:
         line = json.loads([ln for ln in f if ln.startswith("{")][-1])
     label, launches_per = line["config"]["options"], line["roofline"]["launches_per_traversal"]
-    step = ("parent_kernel", "child_kernel")
+    step = LEVEL_KERNELS
 
     trace = _csv(os.path.join(d, "trace"), "kernel_trace.csv")
     rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"])) for r in trace]
@@ -648,7 +651,7 @@ def summarize_profiles(args, d):
     alg = line["roofline"]["algorithmic_bytes_per_launch"]
     # the library's kernels (torch's kernels of the untimed result certificates
     # and the calibration kernel of the probe roofline are left out)
-    ours = ("parent_kernel", "child_kernel", "init_kernel", "admit", "advance", "__amd_rocclr")
+    ours = LEVEL_KERNELS + ("init_kernel", "admit", "advance", "clear_found", "__amd_rocclr")
     top = sorted(((n, v) for n, v in stats.items() if n.startswith(ours)), key=lambda kv: -kv[1][1])[:8]
     md = [f"# {args.workload}: kernel time and HBM traffic ({label})", "",
           "Commands (MI355X, from the repository root, after `export TMPDIR=/tmp`):", "",
@@ -661,7 +664,7 @@ def summarize_profiles(args, d):
     md += ["", f"Traversals traced: {traversals}; level-step launches per traversal "
                f"{launches_per:.4g} (levels + 1).",
            f"Level step (parent_kernel + child_kernel"
-           f"{'; the parent kernel runs as two kernels, pass 1 before and pass 2 after the child kernel' if args.workload.startswith('sssp') else ''}"
+           f"{'; the parent kernel runs as two kernels, pass 1 before and pass 2 after the child kernel' if args.workload.startswith('sssp') else ' + harvest_kernel'}"
            f") kernel time per launch: **{kernel_us:.2f} us** "
            f"(bench line of the traced run: mean_launch_us {line['roofline']['mean_launch_us']}, "
            f"which also holds the gaps between graph nodes).", "",
@@ -794,7 +797,7 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(name, opts.label()),
                 "kernel": (f"level step: parent_kernel + child_kernel"
-                           f"{' + parent_kernel pass 2' if wl.kind == 'sssp' else ''} "
+                           f"{' + parent_kernel pass 2' if wl.kind == 'sssp' else ' + harvest_kernel'} "
                            f"<{wl.kind.upper()}, {opts.label()}>"),
                 "launches_per_traversal": float(launches.mean()),
                 "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
@@ -1328,14 +1331,15 @@ def child_skew(rows, mhz=REALTIME_MHZ):
     return {k: round(v / wsum, 3) if wsum else None for k, v in acc.items()}
 
 
-def level_table(rows, mhz=REALTIME_MHZ):
+def level_table(rows, mhz=REALTIME_MHZ, third="serial"):
     """Per level of one timed traversal: each kernel's span (first entry to last
     exit, us) and, for the child kernel, the mean and the largest workgroup span
-    and the spread of workgroup exits."""
+    and the spread of workgroup exits.  `third` names the level step's third
+    kernel (SSSP: the thresholded children; BFS: the harvest)."""
     out = []
     for L in range(rows.shape[0]):
         row = {"level": L}
-        for k, name in ((0, "parent"), (1, "child"), (2, "serial")):
+        for k, name in ((0, "parent"), (1, "child"), (2, third)):
             r = rows[L, k]
             r = r[r[:, 1] != 0]
             if r.size == 0:
@@ -1362,6 +1366,7 @@ def bench_breakdown(args, dpo, torch):
     dg = dpo.DeviceGraph.from_host(wl.g)
     tuned = TUNED[name]
     Ts = (0, 16, 64) if wl.kind == "bfs" else (0, 128, 512)
+    third = "harvest" if wl.kind == "bfs" else "serial"
     rs, _ = reached_stats(dpo, torch, wl, dg, dpo.Options(**tuned))
     steps = max(r[2]["levels"] for r in rs) + 1
     timing = torch.zeros(dpo.TIMING_BYTES // 8, dtype=torch.int64, device="cuda")
@@ -1389,7 +1394,7 @@ def bench_breakdown(args, dpo, torch):
                 skews.append(child_skew(rows))
                 grids = [int((rows[:, k, :, 1] != 0).sum(axis=1).max()) for k in range(3)]
                 if levels_of is None and T == tuned["threshold"] and CF == tuned["coarsen"]:
-                    levels_of = (int(s), level_table(rows))
+                    levels_of = (int(s), level_table(rows, third=third))
                 for p in phases:
                     acc[p] += tot[p] / len(wl.sources)
                 imb.append(ib)
@@ -1429,7 +1434,9 @@ def bench_breakdown(args, dpo, torch):
           "aggregation = scans, launch records and group counters; launch = publishing grids "
           "and reading the level's published grids, plus the parent-to-child gap; "
           "disaggregation = finding each wave's first record and loading record windows; "
-          "child = the coarsening loop and the child body.  The stamps wait for memory, so "
+          "child = the coarsening loop and the child body (for BFS with per-XCD copies also "
+          "the harvest kernel, which turns a wide level's found vertices into levels and the "
+          "next frontier).  The stamps wait for memory, so "
           "the timed traversal is slower than the product one (both columns shown); the "
           "phase split is of the timed run.", "",
           "## Mean per traversal (us)", "",
@@ -1446,12 +1453,12 @@ def bench_breakdown(args, dpo, torch):
            "|---|---|---|---|---|"]
     md += [f"| {r['threshold']} | {r['coarsen']} | {r['child_skew']['start_spread_us']} | "
            f"{r['child_skew']['end_spread_us']} | {r['child_skew']['xcd_span_ratio']} |" for r in results]
-    md += ["", "Workgroups that stamped rows (largest level; parent, child, thresholded-children "
-           "kernel): " + "; ".join(f"T{r['threshold']} CF{r['coarsen']}: {r['workgroups_with_rows']}"
+    md += ["", "Workgroups that stamped rows (largest level; parent, child, third kernel: "
+           f"{'the harvest' if wl.kind == 'bfs' else 'the thresholded children'}): " + "; ".join(f"T{r['threshold']} CF{r['coarsen']}: {r['workgroups_with_rows']}"
                                    for r in results[:3]) + "."]
     if levels_of is not None:
         src, table = levels_of
-        cols = ["level", "parent_us", "child_us", "serial_us", "child_wg_mean_us", "child_wg_max_us",
+        cols = ["level", "parent_us", "child_us", third + "_us", "child_wg_mean_us", "child_wg_max_us",
                 "child_exit_spread_us", "child_workgroups"]
         md += ["", f"## Per level, tuned options ({tuned['threshold']}, CF {tuned['coarsen']}), "
                    f"source {src}", "", "| " + " | ".join(cols) + " |", "|" + "---|" * len(cols)]

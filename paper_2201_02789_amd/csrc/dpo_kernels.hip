@@ -1288,8 +1288,8 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
 // that bitmap 0 lacks was discovered at this level.  It gets its level, its
 // bit in bitmap 0 and a place in the next frontier (in slot order, which also
 // makes the next level's row loads mostly consecutive).  One lane per slot: a
-// wave reads 64 found bytes and the two bitmap words they map to, and owns
-// those words for the kernel.  Found bytes are never cleared within a
+// run of 64 slots is 64 found bytes and the two bitmap words they map to, which
+// the wave that reads them owns for the kernel.  Found bytes are never cleared within a
 // traversal: one set at an earlier level belongs to a vertex that the harvest
 // of that level put into bitmap 0.  Admission clears a query's found bytes,
 // and a serving engine clears all of them when it is created
@@ -1313,24 +1313,35 @@ __global__ __launch_bounds__(PB) void harvest_kernel(Args a, uint32_t step) {
   int32_t* fout = (L & 1) ? a.front0 : a.front1;
   Stage s{s_stage[wave], 0u};
   const uint32_t n = (uint32_t)a.slots;
-  for (uint32_t b = (blockIdx.x * NW + wave) * 64u; b < n; b += gridDim.x * PB) {
-    const uint32_t v = b + (uint32_t)lane;
-    uint32_t c = 0;
-    bool nw = false;
-    if (v < n) {
-      c = a.visit[v >> 5];
-      nw = a.found[v] != 0 && !((c >> (v & 31)) & 1u);
+  // a single traversal has one level value; with several queries it is looked
+  // up per found vertex
+  const int32_t lv1 = (int32_t)(L + 1) - a.q[0].lstart;
+  // HU runs of 64 slots per wave and round, all their loads issued first
+  constexpr int HU = 4;
+  for (uint32_t b = (blockIdx.x * NW + wave) * (64u * HU); b < n; b += gridDim.x * PB * HU) {
+    uint32_t c[HU];
+    bool f[HU];
+#pragma unroll
+    for (int k = 0; k < HU; ++k) {
+      const uint32_t v = b + (uint32_t)k * 64u + (uint32_t)lane;
+      c[k] = v < n ? a.visit[v >> 5] : ~0u;
+      f[k] = v < n && a.found[v] != 0;
     }
-    const unsigned long long m = __ballot(nw);
-    if (m) {  // wave-uniform
-      if (nw) a.level[v] = (int32_t)(L + 1) - a.q[a.qmap[v >> 5]].lstart;
-      // lanes 0 and 32 own the words of slots b .. b + 31 and b + 32 .. b + 63
-      if ((lane & 31) == 0) {
-        const uint32_t bits = (uint32_t)(m >> (lane & 32));
-        if (bits) a.visit[v >> 5] = c | bits;
+#pragma unroll
+    for (int k = 0; k < HU; ++k) {
+      const uint32_t v = b + (uint32_t)k * 64u + (uint32_t)lane;
+      const bool nw = f[k] && !((c[k] >> (v & 31)) & 1u);
+      const unsigned long long m = __ballot(nw);
+      if (m) {  // wave-uniform
+        if (nw) a.level[v] = a.nq == 1 ? lv1 : (int32_t)(L + 1) - a.q[a.qmap[v >> 5]].lstart;
+        // lanes 0 and 32 own the words of the run's slots 0 .. 31 and 32 .. 63
+        if ((lane & 31) == 0) {
+          const uint32_t bits = (uint32_t)(m >> (lane & 32));
+          if (bits) a.visit[v >> 5] = c[k] | bits;
+        }
       }
+      stage_push(s, nw, (int32_t)v, a, cur, fout, lane);
     }
-    stage_push(s, nw, (int32_t)v, a, cur, fout, lane);
   }
   block_flush(s, a, cur, fout, tid, s_bc);
   pc.mark(TP_CHILD);
