@@ -1229,7 +1229,10 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
               c[u].lv = __builtin_amdgcn_readlane(win.lv, k);
               c[u].du = (uint32_t)__builtin_amdgcn_readlane((int32_t)win.du, k);
               if (e0 + lane < e1 && !((sup >> k) & 1ull)) {
-                v[u] = a.col[e0 + lane];
+                // the level's adjacency is read once: non-temporal, so its
+                // lines leave L2 first and the probed bitmaps and found bytes
+                // stay
+                v[u] = __builtin_nontemporal_load(&a.col[e0 + lane]);
                 if (P == PROB_SSSP) w[u] = a.w[e0 + lane];
               }
             }
