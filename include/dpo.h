@@ -112,19 +112,23 @@ typedef struct {
   int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  BFS levels
                                with at least split_min frontier entries: each
                                XCD (workgroup % 8) probes a visited bitmap of its
-                               own, kept with plain loads and stores, in which a
-                               lane records a claim before sending it; the
-                               claims go to a bitmap that only atomics touch.
-                               Each XCD then sends about one claim per vertex,
-                               and no plain load reads lines the atomics are
-                               updating.  When off, such a level probes a frozen
-                               copy while claiming in a second one.  Narrower
+                               own, kept with plain loads and stores, and a lane
+                               records a new vertex there and as a found byte,
+                               with no atomic; a third kernel after the level
+                               gives every found vertex not visited before it
+                               its level and a place in the next frontier.  When
+                               off, such a level probes a frozen copy while
+                               claiming with atomics in a second one.  Narrower
                                levels probe and claim one bitmap.  Speed only. */
 } dpo_options;
 
 typedef enum {
   DPO_HINT_AUTO = 0,  /* on for single traversals (dpo_bfs and its variants)
-                         and the serving engine, off for dpo_bfs_batch         */
+                         and the serving engine when the graph (the arena for
+                         the engine) has at least 8 directed entries per
+                         vertex; off for dpo_bfs_batch and sparser graphs,
+                         where many narrow levels would each pay the extra
+                         kernel launch                                         */
   DPO_HINT_ON = 1,
   DPO_HINT_OFF = 2
 } dpo_claim_hint;
@@ -164,8 +168,9 @@ void dpo_default_options(dpo_options* o);
  * vertex for large graphs.  0 on bad args.
  * Layout, all inside the caller's buffer: traversal state and counters, two
  * frontier buffers (64 sharded queues plus an overflow queue), a per-vertex
- * visit word (for BFS two visited bitmaps and one per XCD, for SSSP iteration
- * stamps), a second distance array (SSSP), launch records of 24 bytes per
+ * visit word (for BFS two visited bitmaps, one per XCD and a found byte per
+ * vertex, for SSSP iteration stamps), a second distance array (SSSP), launch
+ * records of 24 bytes per
  * vertex, a list
  * of thresholded parents of 16 bytes per vertex, 8 descriptor queues of 16
  * bytes per possible aggregated grid and per-workgroup counters. */

@@ -129,7 +129,7 @@ struct CachedGraph {
   const void* parent;
   const void* child;
   const void* third;
-  int pgrid, cgrid, steps;
+  int pgrid, cgrid, tgrid, steps;
   Args args;
   hipGraphExec_t exec;
   uint64_t last_use;
@@ -223,15 +223,15 @@ dpo_status add_node(hipGraph_t graph, hipGraphNode_t* prev, const void* fn, int 
 }
 
 // K level steps (parent kernel, then child kernel unless flat, then the third
-// kernel if any, on the parent kernel's grid: SSSP's thresholded children or
+// kernel if any: SSSP's thresholded children, on the parent kernel's grid, or
 // BFS's harvest) and the advance of the level base, as one instantiated graph.
 dpo_status get_exec(Runtime& r, const void* parent, const void* child, const void* third,
-                    int pgrid, int cgrid, int steps, const Args& args, hipGraphExec_t* out,
-                    bool cached = true) {
+                    int pgrid, int cgrid, int tgrid, int steps, const Args& args,
+                    hipGraphExec_t* out, bool cached = true) {
   for (auto& e : r.graphs) {
     if (!cached) break;
     if (e.parent == parent && e.child == child && e.third == third && e.pgrid == pgrid &&
-        e.cgrid == cgrid &&
+        e.cgrid == cgrid && e.tgrid == tgrid &&
         e.steps == steps && std::memcmp(&e.args, &args, sizeof(Args)) == 0) {
       e.last_use = ++r.tick;
       *out = e.exec;
@@ -249,7 +249,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, const voi
     void* params[] = {&a, &step_ids[i]};
     s = add_node(graph, &prev, parent, pgrid, PB, params);
     if (s == DPO_OK && child) s = add_node(graph, &prev, child, cgrid, PB, params);
-    if (s == DPO_OK && third) s = add_node(graph, &prev, third, pgrid, PB, params);
+    if (s == DPO_OK && third) s = add_node(graph, &prev, third, tgrid, PB, params);
   }
   State* st = a.st;
   uint32_t k = (uint32_t)steps;
@@ -271,7 +271,8 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, const voi
     (void)hipGraphExecDestroy(r.graphs[victim].exec);
     r.graphs.erase(r.graphs.begin() + victim);
   }
-  r.graphs.push_back(CachedGraph{parent, child, third, pgrid, cgrid, steps, args, exec, ++r.tick});
+  r.graphs.push_back(
+      CachedGraph{parent, child, third, pgrid, cgrid, tgrid, steps, args, exec, ++r.tick});
   *out = exec;
   return DPO_OK;
 }
@@ -287,7 +288,7 @@ struct SetRun {
   // after the child kernel: SSSP's thresholded children, or BFS's harvest
   // (per-XCD copies)
   const void* third = nullptr;
-  int pgrid = 0, cgrid = 0, steps = kDefaultSteps;
+  int pgrid = 0, cgrid = 0, tgrid = 0, steps = kDefaultSteps;
   hipStream_t stream = nullptr;
   int32_t* qlist = nullptr;  // device: indices of the queries being admitted
 };
@@ -304,9 +305,18 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   const int gran = gran_of(o);
   sr->problem = problem;
   sr->lay = lay;
+  // BFS per-XCD copies: single traversals and the serving engine (not a batch
+  // call) on graphs whose average degree is at least HINT_AUTO_MIN_DEGREE,
+  // unless the options say otherwise.  The harvest adds a kernel launch to
+  // every level step; a graph of low average degree runs many narrow levels
+  // and rarely a wide one.
+  const bool dense = g->m >= (int64_t)HINT_AUTO_MIN_DEGREE * g->n;
+  const bool hint = problem == PROB_BFS &&
+                    (o.claim_hint == DPO_HINT_ON ||
+                     (o.claim_hint == DPO_HINT_AUTO && !batch_call && dense));
   sr->parent = parent_kernel_ptr(problem, gran);
-  sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem);
-  sr->third = serial_kernel_ptr(problem, gran);
+  sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem, false, hint);
+  sr->third = hint ? harvest_kernel_ptr() : serial_kernel_ptr(problem, gran);
   if (!sr->parent) return DPO_ERR_UNSUPPORTED;
   char* base = (char*)ws;
   Args& a = sr->a;
@@ -343,9 +353,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.split_min = o.split_min;
   a.serial_wave = o.serial_wave;
   a.dyn_pct = o.dyn_share;
-  a.hint = problem == PROB_BFS &&
-           (o.claim_hint == DPO_HINT_ON || (o.claim_hint == DPO_HINT_AUTO && !batch_call));
-  if (a.hint) sr->third = harvest_kernel_ptr();
+  a.hint = hint ? 1 : 0;
   a.ngroups_cap = lay.ngroups_cap;
   a.desc_cap = lay.desc_cap;
   a.fcap = lay.fcap;
@@ -353,22 +361,28 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   sr->qlist = (int32_t*)(base + lay.qlist);
   sr->pgrid = persistent_grid(r, sr->parent);
   // the thresholded children's kernel walks the lists of the parent kernel's
-  // workgroups: one grid for both, all of it resident in either (the harvest
-  // runs on any grid)
-  if (sr->third && !a.hint) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
+  // workgroups: one grid for both, all of it resident in either
+  if (sr->third && !hint) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
   sr->cgrid = sr->child ? persistent_grid(r, sr->child) : 0;
+  // the harvest: as many workgroups as its rounds need, at most the parent
+  // grid (a small graph's many narrow levels launch it empty)
+  sr->tgrid = !sr->third ? 0
+              : !hint    ? sr->pgrid
+                         : (int)std::min<int64_t>(sr->pgrid, cdiv(slots, (int64_t)PB * HARVEST_RUNS));
   sr->steps = o.steps_per_replay ? o.steps_per_replay : kDefaultSteps;
   sr->stream = (hipStream_t)stream;
   if (tm) {
     sr->parent = parent_kernel_ptr(problem, gran, true);
-    sr->child = sr->child ? child_kernel_ptr(problem, true) : nullptr;
-    sr->third = a.hint ? harvest_kernel_ptr(true) : serial_kernel_ptr(problem, gran, true);
+    sr->child = sr->child ? child_kernel_ptr(problem, true, hint) : nullptr;
+    sr->third = hint ? harvest_kernel_ptr(true) : serial_kernel_ptr(problem, gran, true);
     // a timed kernel that needs more registers than its product one runs on
     // the grid that is resident at its own occupancy (a larger grid would run
     // in two rounds and time the second round's wait as work)
     sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->parent));
-    if (sr->third) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
+    if (sr->third && !hint) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
     if (sr->child) sr->cgrid = std::min(sr->cgrid, persistent_grid(r, sr->child));
+    sr->tgrid = !sr->third ? 0 : !hint ? sr->pgrid
+                : std::min(sr->tgrid, persistent_grid(r, sr->third));
     a.tm = tm;
   }
   return DPO_OK;
@@ -454,7 +468,7 @@ dpo_status replay(Runtime& r, SetRun& sr, hipGraphExec_t exec) {
 dpo_status run_to_completion(Runtime& r, SetRun& sr, int64_t max_levels) {
   hipGraphExec_t exec;
   dpo_status s =
-      get_exec(r, sr.parent, sr.child, sr.third, sr.pgrid, sr.cgrid, sr.steps, sr.a, &exec);
+      get_exec(r, sr.parent, sr.child, sr.third, sr.pgrid, sr.cgrid, sr.tgrid, sr.steps, sr.a, &exec);
   if (s != DPO_OK) return s;
   const int64_t max_replays = max_levels / sr.steps + 2;
   for (int64_t rep = 0; rep < max_replays; ++rep) {
@@ -617,7 +631,7 @@ dpo_status launch_step(SetRun& sr, uint32_t step) {
       hipLaunchKernel(sr.child, dim3((unsigned)sr.cgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
   if (sr.third &&
-      hipLaunchKernel(sr.third, dim3((unsigned)sr.pgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
+      hipLaunchKernel(sr.third, dim3((unsigned)sr.tgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
   return DPO_OK;
 }
@@ -880,7 +894,7 @@ dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_opt
     e->hlist = (int32_t*)(e->hq + max_queries);
     std::memset(e->hq, 0, (size_t)max_queries * sizeof(Query));
     s = get_exec(r, e->sr.parent, e->sr.child, e->sr.third, e->sr.pgrid, e->sr.cgrid,
-                 e->sr.steps, e->sr.a, &e->exec, false);
+                 e->sr.tgrid, e->sr.steps, e->sr.a, &e->exec, false);
   }
   if (s == DPO_OK) s = start_set(r, e->sr);
   if (s == DPO_OK && e->sr.a.hint) {

@@ -22,6 +22,9 @@ constexpr int ADMIT_CHUNK = 4096;  // output slots initialised per admit workgro
 constexpr int PRECHECK_MIN = 32;   // claim candidates per 512-lane batch above which
                                    // a coherent load precedes the atomics
 constexpr int NHINT = 8;           // BFS per-XCD visited copies (Args::hint), one per XCD
+constexpr int HARVEST_RUNS = 4;    // harvest kernel: 64-slot runs per wave and round
+constexpr int HINT_AUTO_MIN_DEGREE = 8;  // DPO_HINT_AUTO: per-XCD copies from this average
+                                         // degree (m / n) up
 
 enum { PROB_BFS = 0, PROB_SSSP = 1 };
 enum { AGG_NONE = 0, AGG_WAVE = 1, AGG_BLOCK = 2, AGG_MULTI = 3, AGG_FLAT = 4 };
@@ -134,7 +137,9 @@ struct Args {
 
 // timed: the instantiation that stamps its phases into Args::tm
 const void* parent_kernel_ptr(int problem, int gran, bool timed = false);
-const void* child_kernel_ptr(int problem, bool timed = false);
+// nt: the child kernel's adjacency loads are non-temporal (used with the
+// per-XCD copies, Args::hint)
+const void* child_kernel_ptr(int problem, bool timed = false, bool nt = false);
 const void* serial_kernel_ptr(int problem, int gran, bool timed = false);
 const void* harvest_kernel_ptr(bool timed = false);
 const void* init_kernel_ptr(int problem);

@@ -1102,7 +1102,7 @@ __device__ __forceinline__ Window load_window(const Args& a, const uint32_t* cla
 // blocks: the parent of its first block is found by search (the
 // disaggregation of Sec. V-A), then records are taken 64 at a time and their
 // slices U at a time.
-template <int P, bool TM>
+template <int P, bool TM, bool NT>
 __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_bc[NW + 8];
@@ -1229,10 +1229,11 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
               c[u].lv = __builtin_amdgcn_readlane(win.lv, k);
               c[u].du = (uint32_t)__builtin_amdgcn_readlane((int32_t)win.du, k);
               if (e0 + lane < e1 && !((sup >> k) & 1ull)) {
-                // the level's adjacency is read once: non-temporal, so its
-                // lines leave L2 first and the probed bitmaps and found bytes
-                // stay
-                v[u] = __builtin_nontemporal_load(&a.col[e0 + lane]);
+                // NT (single traversals with per-XCD copies): the level's
+                // adjacency is read once, so its lines leave L2 first and the
+                // probed bitmaps and found bytes stay.  A batch of many
+                // traversals over few graphs reads each adjacency again.
+                v[u] = NT ? __builtin_nontemporal_load(&a.col[e0 + lane]) : a.col[e0 + lane];
                 if (P == PROB_SSSP) w[u] = a.w[e0 + lane];
               }
             }
@@ -1320,7 +1321,7 @@ __global__ __launch_bounds__(PB) void harvest_kernel(Args a, uint32_t step) {
   // up per found vertex
   const int32_t lv1 = (int32_t)(L + 1) - a.q[0].lstart;
   // HU runs of 64 slots per wave and round, all their loads issued first
-  constexpr int HU = 4;
+  constexpr int HU = HARVEST_RUNS;
   for (uint32_t b = (blockIdx.x * NW + wave) * (64u * HU); b < n; b += gridDim.x * PB * HU) {
     uint32_t c[HU];
     bool f[HU];
@@ -1494,12 +1495,16 @@ const void* harvest_kernel_ptr(bool timed) {
   return timed ? (const void*)harvest_kernel<true> : (const void*)harvest_kernel<false>;
 }
 
-const void* child_kernel_ptr(int problem, bool timed) {
-  if (timed)
-    return problem == PROB_BFS ? (const void*)child_kernel<PROB_BFS, true>
-                               : (const void*)child_kernel<PROB_SSSP, true>;
-  return problem == PROB_BFS ? (const void*)child_kernel<PROB_BFS, false>
-                             : (const void*)child_kernel<PROB_SSSP, false>;
+template <bool TM>
+static const void* child_ptr(int problem, bool nt) {
+  if (problem == PROB_BFS)
+    return nt ? (const void*)child_kernel<PROB_BFS, TM, true>
+              : (const void*)child_kernel<PROB_BFS, TM, false>;
+  return (const void*)child_kernel<PROB_SSSP, TM, false>;
+}
+
+const void* child_kernel_ptr(int problem, bool timed, bool nt) {
+  return timed ? child_ptr<true>(problem, nt) : child_ptr<false>(problem, nt);
 }
 
 const void* init_kernel_ptr(int) { return (const void*)init_kernel; }

@@ -393,7 +393,9 @@ class Engine:
     """
 
     def __init__(self, arena: DeviceArena, kind: str, bucket_opts, graph_bucket=None,
-                 max_queries: int = 256, max_slots: int = 1 << 22, stream=None):
+                 max_queries: int = 256, max_slots: int = 1 << 22, stream=None, workspace=None):
+        """workspace: optional device uint8 tensor of at least
+        dpo_engine_workspace_bytes; allocated here when None."""
         import torch
         self.arena = arena
         self.kind = kind
@@ -404,7 +406,13 @@ class Engine:
         if nbytes == 0:
             raise DpoError(DPO_ERR_ARG, "dpo_engine_workspace_bytes")
         dev = arena.graph.row_ptr.device
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        if workspace is None:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        else:
+            if workspace.numel() * workspace.element_size() < nbytes:
+                raise DpoError(DPO_ERR_WORKSPACE, "Engine workspace")
+            self.ws = workspace
+            nbytes = workspace.numel() * workspace.element_size()
         self.scratch = torch.empty(((max_slots + 31) // 32) * 32, dtype=torch.int32, device=dev)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._gb = None

@@ -83,6 +83,42 @@ def test_engine_results_match_oracle_and_lone_runs(resident, kind, agg, steps, s
         assert np.array_equal(lone.cpu().numpy(), o.cpu().numpy())
 
 
+@pytest.mark.parametrize("kind", ["bfs", "sssp"])
+def test_engine_on_a_dirty_workspace(resident, kind):
+    """An engine built on a workspace full of stale bytes: its arena has slots
+    that no query has been admitted to, which the kernels must never take for
+    found or queued vertices (every level wide, so every BFS level ends in the
+    harvest).  Every result equals the oracle."""
+    graphs, da = resident
+    bopts = [dpo.Options(threshold=16, coarsen=1, steps_per_replay=3, split_min=0)]
+    probe = dpo.Engine(da, kind, bopts, max_queries=4, max_slots=12 * 1024)
+    nbytes = probe.ws.numel()
+    probe.close()
+    ws = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
+    eng = dpo.Engine(da, kind, bopts, max_queries=4, max_slots=12 * 1024, workspace=ws)
+    outs = {}
+    for g in (0, 2, 4, 1, 3):  # the footprint pool holds a few graphs at once
+        s = int(gg.sample_sources(graphs[g], 1, 77 + g)[0])
+        o = torch.full((graphs[g].n,), -9, dtype=torch.int32, device="cuda")
+        outs[eng.submit(g, s, o)] = (g, s, o)
+    done = set()
+    for _ in range(2000):
+        run, pend = eng.step()
+        done.update(eng.poll())
+        if run == 0 and pend == 0:
+            break
+    done.update(eng.poll())
+    eng.close()
+    torch.cuda.synchronize()
+    assert done == set(outs)
+    for t, (g, s, o) in outs.items():
+        if kind == "bfs":
+            want, _ = oracle.bfs(graphs[g], s)
+            assert np.array_equal(o.cpu().numpy(), want), (t, g, s)
+        else:
+            assert np.array_equal(dpo.as_uint32(o), oracle.dijkstra(graphs[g], s)), (t, g, s)
+
+
 def test_engine_rejects_oversized_and_bad_queries(resident):
     graphs, da = resident
     eng = dpo.Engine(da, "bfs", [dpo.Options()], max_queries=4, max_slots=1024)
