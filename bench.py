@@ -103,7 +103,9 @@ def agg_of(s):
 # and smaller blocks make equal block counts closer to equal edge counts.
 TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128, dyn_share=25,
                        split_min=4096),
-         "er22": dict(threshold=8, coarsen=1, agg=3, agg_blocks=4, child_block=128, split_min=4096),
+         # above the maximum degree (62): nothing launches, the waves run every
+         # child together; wave granularity keeps pass 1 free of block barriers
+         "er22": dict(threshold=128, coarsen=1, agg=1, child_block=128, split_min=4096),
          "bfs25": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block=128),
          "bfs12": dict(threshold=32, coarsen=8, agg=3, agg_blocks=4),
          "sssp21": dict(threshold=512, coarsen=1, agg=3, agg_blocks=4, split_min=262144,
