@@ -247,7 +247,7 @@ def reached_stats(dpo, torch, wl, dg, opts):
     return res, passed
 
 
-# the kernels of a level step (SSSP runs parent_kernel twice; BFS single
+# the kernels of a level step (SSSP runs parent_kernel twice; single
 # traversals add the harvest)
 LEVEL_KERNELS = ("parent_kernel", "child_kernel", "harvest_kernel")
 KERNEL_SOURCES = ["paper_2201_02789_amd/csrc/dpo_kernels.hip",
@@ -666,7 +666,7 @@ def summarize_profiles(args, d):
     md += ["", f"Traversals traced: {traversals}; level-step launches per traversal "
                f"{launches_per:.4g} (levels + 1).",
            f"Level step (parent_kernel + child_kernel"
-           f"{'; the parent kernel runs as two kernels, pass 1 before and pass 2 after the child kernel' if args.workload.startswith('sssp') else ' + harvest_kernel'}"
+           f" + harvest_kernel{'; the parent kernel runs as two kernels, pass 1 before and pass 2 after the child kernel' if args.workload.startswith('sssp') else ''}"
            f") kernel time per launch: **{kernel_us:.2f} us** "
            f"(bench line of the traced run: mean_launch_us {line['roofline']['mean_launch_us']}, "
            f"which also holds the gaps between graph nodes).", "",
@@ -799,7 +799,7 @@ def workload_line(args, dpo, torch, name, steps, warmup, with_cpu, with_baseline
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(name, opts.label()),
                 "kernel": (f"level step: parent_kernel + child_kernel"
-                           f"{' + parent_kernel pass 2' if wl.kind == 'sssp' else ' + harvest_kernel'} "
+                           f"{' + parent_kernel pass 2' if wl.kind == 'sssp' else ''} + harvest_kernel "
                            f"<{wl.kind.upper()}, {opts.label()}>"),
                 "launches_per_traversal": float(launches.mean()),
                 "mean_launch_us": round(float(mean_call_ms.sum() / launches.sum() * 1e3), 2),
@@ -1263,7 +1263,7 @@ REALTIME_MHZ = 100.0  # the constant-rate clock the timed kernels stamp
 def phase_split(rows, mhz=REALTIME_MHZ):
     """Execution-time breakdown of one timed traversal (Sec. VIII-B).
 
-    rows: uint64 [levels, 3 kernels, workgroups, 8] as written by
+    rows: uint64 [levels, 4 kernels, workgroups, 8] as written by
     dpo_traverse_timed.  Per level and kernel, the kernel's span (first
     workgroup entry to last exit) is split among the phases in proportion to
     the cycles its waves spent in each; the gap from the parent kernel's end to
@@ -1333,15 +1333,15 @@ def child_skew(rows, mhz=REALTIME_MHZ):
     return {k: round(v / wsum, 3) if wsum else None for k, v in acc.items()}
 
 
-def level_table(rows, mhz=REALTIME_MHZ, third="serial"):
+def level_table(rows, mhz=REALTIME_MHZ):
     """Per level of one timed traversal: each kernel's span (first entry to last
     exit, us) and, for the child kernel, the mean and the largest workgroup span
-    and the spread of workgroup exits.  `third` names the level step's third
-    kernel (SSSP: the thresholded children; BFS: the harvest)."""
+    and the spread of workgroup exits (kernels: parent, child, SSSP's
+    thresholded children, harvest)."""
     out = []
     for L in range(rows.shape[0]):
         row = {"level": L}
-        for k, name in ((0, "parent"), (1, "child"), (2, third)):
+        for k, name in ((0, "parent"), (1, "child"), (2, "serial"), (3, "harvest")):
             r = rows[L, k]
             r = r[r[:, 1] != 0]
             if r.size == 0:
@@ -1368,7 +1368,6 @@ def bench_breakdown(args, dpo, torch):
     dg = dpo.DeviceGraph.from_host(wl.g)
     tuned = TUNED[name]
     Ts = (0, 16, 64) if wl.kind == "bfs" else (0, 128, 512)
-    third = "harvest" if wl.kind == "bfs" else "serial"
     rs, _ = reached_stats(dpo, torch, wl, dg, dpo.Options(**tuned))
     steps = max(r[2]["levels"] for r in rs) + 1
     timing = torch.zeros(dpo.TIMING_BYTES // 8, dtype=torch.int64, device="cuda")
@@ -1391,12 +1390,12 @@ def bench_breakdown(args, dpo, torch):
                 e1.record(stream)
                 torch.cuda.synchronize()
                 timed_ms.append(e0.elapsed_time(e1))
-                rows = timing.cpu().numpy().view(np.uint64).reshape(64, 3, 4096, 8)
+                rows = timing.cpu().numpy().view(np.uint64).reshape(64, 4, 4096, 8)
                 tot, per_level, ib = phase_split(rows)
                 skews.append(child_skew(rows))
-                grids = [int((rows[:, k, :, 1] != 0).sum(axis=1).max()) for k in range(3)]
+                grids = [int((rows[:, k, :, 1] != 0).sum(axis=1).max()) for k in range(4)]
                 if levels_of is None and T == tuned["threshold"] and CF == tuned["coarsen"]:
-                    levels_of = (int(s), level_table(rows, third=third))
+                    levels_of = (int(s), level_table(rows))
                 for p in phases:
                     acc[p] += tot[p] / len(wl.sources)
                 imb.append(ib)
@@ -1436,9 +1435,9 @@ def bench_breakdown(args, dpo, torch):
           "aggregation = scans, launch records and group counters; launch = publishing grids "
           "and reading the level's published grids, plus the parent-to-child gap; "
           "disaggregation = finding each wave's first record and loading record windows; "
-          "child = the coarsening loop and the child body (for BFS with per-XCD copies also "
-          "the harvest kernel, which turns a wide level's found vertices into levels and the "
-          "next frontier).  The stamps wait for memory, so "
+          "child = the coarsening loop and the child body (also the harvest kernel, which "
+          "turns a level's found vertices into the next frontier, with their levels for "
+          "BFS).  The stamps wait for memory, so "
           "the timed traversal is slower than the product one (both columns shown); the "
           "phase split is of the timed run.", "",
           "## Mean per traversal (us)", "",
@@ -1455,12 +1454,13 @@ def bench_breakdown(args, dpo, torch):
            "|---|---|---|---|---|"]
     md += [f"| {r['threshold']} | {r['coarsen']} | {r['child_skew']['start_spread_us']} | "
            f"{r['child_skew']['end_spread_us']} | {r['child_skew']['xcd_span_ratio']} |" for r in results]
-    md += ["", "Workgroups that stamped rows (largest level; parent, child, third kernel: "
-           f"{'the harvest' if wl.kind == 'bfs' else 'the thresholded children'}): " + "; ".join(f"T{r['threshold']} CF{r['coarsen']}: {r['workgroups_with_rows']}"
-                                   for r in results[:3]) + "."]
+    md += ["", "Workgroups that stamped rows (largest level; parent, child, thresholded-children "
+           "and harvest kernel): " + "; ".join(f"T{r['threshold']} CF{r['coarsen']}: {r['workgroups_with_rows']}"
+                                               for r in results[:3]) + "."]
     if levels_of is not None:
         src, table = levels_of
-        cols = ["level", "parent_us", "child_us", third + "_us", "child_wg_mean_us", "child_wg_max_us",
+        cols = ["level", "parent_us", "child_us"] + (["serial_us"] if wl.kind == "sssp" else []) + [
+                "harvest_us", "child_wg_mean_us", "child_wg_max_us",
                 "child_exit_spread_us", "child_workgroups"]
         md += ["", f"## Per level, tuned options ({tuned['threshold']}, CF {tuned['coarsen']}), "
                    f"source {src}", "", "| " + " | ".join(cols) + " |", "|" + "---|" * len(cols)]

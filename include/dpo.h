@@ -109,26 +109,31 @@ typedef struct {
                                left (as a hardware block scheduler hands out
                                blocks), so waves whose blocks run slow do fewer.
                                Speed only.                                      */
-  int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  BFS levels
+  int32_t claim_hint;       /* dpo_claim_hint, default DPO_HINT_AUTO.  Found bytes
+                               and a harvest kernel after the level.  BFS levels
                                with at least split_min frontier entries: each
                                XCD (workgroup % 8) probes a visited bitmap of its
                                own, kept with plain loads and stores, and a lane
                                records a new vertex there and as a found byte,
-                               with no atomic; a third kernel after the level
-                               gives every found vertex not visited before it
-                               its level and a place in the next frontier.  When
-                               off, such a level probes a frozen copy while
-                               claiming with atomics in a second one.  Narrower
-                               levels probe and claim one bitmap.  Speed only. */
+                               with no atomic; the harvest gives every found
+                               vertex not visited before it its level and a
+                               place in the next frontier.  When off, such a
+                               level probes a frozen copy while claiming with
+                               atomics in a second one.  Narrower levels probe
+                               and claim one bitmap.  SSSP, every level: a lane
+                               whose atomicMin improved a distance records the
+                               vertex as found, and the harvest queues it once;
+                               when off, an iteration stamp exchanged
+                               atomically does.  Speed only.                    */
 } dpo_options;
 
 typedef enum {
-  DPO_HINT_AUTO = 0,  /* on for single traversals (dpo_bfs and its variants)
-                         and the serving engine when the graph (the arena for
-                         the engine) has at least 8 directed entries per
-                         vertex; off for dpo_bfs_batch and sparser graphs,
-                         where many narrow levels would each pay the extra
-                         kernel launch                                         */
+  DPO_HINT_AUTO = 0,  /* on for single traversals (dpo_bfs, dpo_sssp and
+                         their variants) and the serving engines when the graph
+                         (the arena for an engine) has at least 8 directed
+                         entries per vertex; off for the batch calls and
+                         sparser graphs, where many narrow levels would each
+                         pay the extra kernel launch                           */
   DPO_HINT_ON = 1,
   DPO_HINT_OFF = 2
 } dpo_claim_hint;
@@ -169,8 +174,8 @@ void dpo_default_options(dpo_options* o);
  * Layout, all inside the caller's buffer: traversal state and counters, two
  * frontier buffers (64 sharded queues plus an overflow queue), a per-vertex
  * visit word (for BFS two visited bitmaps, one per XCD and a found byte per
- * vertex, for SSSP iteration stamps), a second distance array (SSSP), launch
- * records of 24 bytes per
+ * vertex, for SSSP iteration stamps or found bytes), a second distance array
+ * (SSSP), launch records of 24 bytes per
  * vertex, a list
  * of thresholded parents of 16 bytes per vertex, 8 descriptor queues of 16
  * bytes per possible aggregated grid and per-workgroup counters. */
@@ -227,9 +232,9 @@ dpo_status dpo_bfs_noalloc(const dpo_csr* g, int32_t source, const dpo_options* 
  * slower than the product one), and each workgroup of each level kernel
  * writes one row of 8 uint64 words to `timing` (device, caller-owned, at
  * least DPO_TIMING_BYTES, zeroed by the call) at index
- *   ((level * 3 + kernel) * 4096 + workgroup) * 8,
+ *   ((level * 4 + kernel) * 4096 + workgroup) * 8,
  * kernel 0 = parent kernel, 1 = child kernel, 2 = SSSP's thresholded-children
- * kernel; words: [0] a constant-rate (100 MHz) clock at the workgroup's entry,
+ * kernel, 3 = the harvest kernel (found bytes, claim_hint); words: [0] a constant-rate (100 MHz) clock at the workgroup's entry,
  * [1] at its exit, [2..6] the cycles its waves spent in parent work,
  * aggregation, launch (publishing a grid; reading the level's published
  * grids), disaggregation (finding records, loading record windows) and child
@@ -237,7 +242,7 @@ dpo_status dpo_bfs_noalloc(const dpo_csr* g, int32_t source, const dpo_options* 
  * zeros: the workgroup did not run (or the level index is 64 or more).
  * Counters are not collected.  Otherwise as dpo_bfs / dpo_sssp;
  * DPO_ERR_ARG if kind, timing or timing_bytes are invalid. */
-#define DPO_TIMING_BYTES (64u * 3u * 4096u * 8u * 8u)
+#define DPO_TIMING_BYTES (64u * 4u * 4096u * 8u * 8u)
 
 dpo_status dpo_traverse_timed(int32_t kind, const dpo_csr* g, int32_t source, const dpo_options* o,
                               void* out, void* ws, size_t ws_bytes, void* stream, void* timing,

@@ -35,8 +35,8 @@ struct Layout {
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t round32(int64_t x) { return (x + 31) & ~(int64_t)31; }
 
-// BFS: byte offset of the found bytes in the visit region, after the two
-// bitmaps and the per-XCD copies
+// Byte offset of the found bytes in the visit region (BFS: after the two
+// bitmaps and the per-XCD copies)
 size_t found_offset(int64_t slots) { return align_up((size_t)(2 + NHINT) * cdiv(slots, 32) * 4); }
 
 int gran_of(const dpo_options& o) {
@@ -87,7 +87,8 @@ Layout layout_for(int64_t slots, int32_t nq, const dpo_options& o) {
   L.grp_done = off; off = align_up(off + 3 * (size_t)L.ngroups_cap * 4);
   L.front0 = off; off = align_up(off + fslots * 4);
   L.front1 = off; off = align_up(off + fslots * 4);
-  // SSSP stamps / two BFS bitmaps, the NHINT per-XCD copies and the found bytes
+  // SSSP stamps / two BFS bitmaps and the NHINT per-XCD copies; then the found
+  // bytes (which SSSP, having no stamps when it uses them, lets overlap these)
   L.visit = off; off = align_up(off + std::max((size_t)slots * 4, found_offset(slots) + (size_t)cdiv(slots, 32) * 32));
   L.dist2 = off; off = align_up(off + (size_t)slots * 4);  // SSSP second distance array
   L.rec = off; off = align_up(off + (size_t)slots * 16);
@@ -129,7 +130,8 @@ struct CachedGraph {
   const void* parent;
   const void* child;
   const void* third;
-  int pgrid, cgrid, tgrid, steps;
+  const void* fourth;
+  int pgrid, cgrid, tgrid, fgrid, steps;
   Args args;
   hipGraphExec_t exec;
   uint64_t last_use;
@@ -224,14 +226,15 @@ dpo_status add_node(hipGraph_t graph, hipGraphNode_t* prev, const void* fn, int 
 
 // K level steps (parent kernel, then child kernel unless flat, then the third
 // kernel if any: SSSP's thresholded children, on the parent kernel's grid, or
-// BFS's harvest) and the advance of the level base, as one instantiated graph.
+// BFS's harvest; then the fourth if any: SSSP's harvest) and the advance of the
+// level base, as one instantiated graph.
 dpo_status get_exec(Runtime& r, const void* parent, const void* child, const void* third,
-                    int pgrid, int cgrid, int tgrid, int steps, const Args& args,
-                    hipGraphExec_t* out, bool cached = true) {
+                    const void* fourth, int pgrid, int cgrid, int tgrid, int fgrid, int steps,
+                    const Args& args, hipGraphExec_t* out, bool cached = true) {
   for (auto& e : r.graphs) {
     if (!cached) break;
-    if (e.parent == parent && e.child == child && e.third == third && e.pgrid == pgrid &&
-        e.cgrid == cgrid && e.tgrid == tgrid &&
+    if (e.parent == parent && e.child == child && e.third == third && e.fourth == fourth &&
+        e.pgrid == pgrid && e.cgrid == cgrid && e.tgrid == tgrid && e.fgrid == fgrid &&
         e.steps == steps && std::memcmp(&e.args, &args, sizeof(Args)) == 0) {
       e.last_use = ++r.tick;
       *out = e.exec;
@@ -250,6 +253,7 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, const voi
     s = add_node(graph, &prev, parent, pgrid, PB, params);
     if (s == DPO_OK && child) s = add_node(graph, &prev, child, cgrid, PB, params);
     if (s == DPO_OK && third) s = add_node(graph, &prev, third, tgrid, PB, params);
+    if (s == DPO_OK && fourth) s = add_node(graph, &prev, fourth, fgrid, PB, params);
   }
   State* st = a.st;
   uint32_t k = (uint32_t)steps;
@@ -272,7 +276,8 @@ dpo_status get_exec(Runtime& r, const void* parent, const void* child, const voi
     r.graphs.erase(r.graphs.begin() + victim);
   }
   r.graphs.push_back(
-      CachedGraph{parent, child, third, pgrid, cgrid, tgrid, steps, args, exec, ++r.tick});
+      CachedGraph{parent, child, third, fourth, pgrid, cgrid, tgrid, fgrid, steps, args, exec,
+                  ++r.tick});
   *out = exec;
   return DPO_OK;
 }
@@ -286,9 +291,10 @@ struct SetRun {
   const void* parent = nullptr;
   const void* child = nullptr;
   // after the child kernel: SSSP's thresholded children, or BFS's harvest
-  // (per-XCD copies)
+  // (per-XCD copies); then SSSP's harvest (found bytes)
   const void* third = nullptr;
-  int pgrid = 0, cgrid = 0, tgrid = 0, steps = kDefaultSteps;
+  const void* fourth = nullptr;
+  int pgrid = 0, cgrid = 0, tgrid = 0, fgrid = 0, steps = kDefaultSteps;
   hipStream_t stream = nullptr;
   int32_t* qlist = nullptr;  // device: indices of the queries being admitted
 };
@@ -305,18 +311,19 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   const int gran = gran_of(o);
   sr->problem = problem;
   sr->lay = lay;
-  // BFS per-XCD copies: single traversals and the serving engine (not a batch
-  // call) on graphs whose average degree is at least HINT_AUTO_MIN_DEGREE,
-  // unless the options say otherwise.  The harvest adds a kernel launch to
-  // every level step; a graph of low average degree runs many narrow levels
-  // and rarely a wide one.
+  // Found bytes and the harvest (BFS: with per-XCD copies): single traversals
+  // and the serving engine (not a batch call) on graphs whose average degree
+  // is at least HINT_AUTO_MIN_DEGREE, unless the options say otherwise.  The
+  // harvest adds a kernel launch to every level step; a graph of low average
+  // degree runs many narrow levels and rarely a wide one.
   const bool dense = g->m >= (int64_t)HINT_AUTO_MIN_DEGREE * g->n;
-  const bool hint = problem == PROB_BFS &&
-                    (o.claim_hint == DPO_HINT_ON ||
-                     (o.claim_hint == DPO_HINT_AUTO && !batch_call && dense));
+  const bool hint = o.claim_hint == DPO_HINT_ON ||
+                    (o.claim_hint == DPO_HINT_AUTO && !batch_call && dense);
+  const bool bfs = problem == PROB_BFS;
   sr->parent = parent_kernel_ptr(problem, gran);
-  sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem, false, hint);
-  sr->third = hint ? harvest_kernel_ptr() : serial_kernel_ptr(problem, gran);
+  sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem, false, bfs && hint);
+  sr->third = bfs ? (hint ? harvest_kernel_ptr(problem) : nullptr) : serial_kernel_ptr(problem, gran);
+  sr->fourth = !bfs && hint ? harvest_kernel_ptr(problem) : nullptr;
   if (!sr->parent) return DPO_ERR_UNSUPPORTED;
   char* base = (char*)ws;
   Args& a = sr->a;
@@ -333,7 +340,8 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   a.front0 = (int32_t*)(base + lay.front0);
   a.front1 = (int32_t*)(base + lay.front1);
   a.visit = (uint32_t*)(base + lay.visit);
-  a.found = problem == PROB_BFS ? (uint8_t*)(base + lay.visit + found_offset(slots)) : nullptr;
+  // SSSP with found bytes has no iteration stamps: the bytes overlap them
+  a.found = (uint8_t*)(base + lay.visit + found_offset(slots));
   a.dist2 = problem == PROB_SSSP ? (uint32_t*)(base + lay.dist2) : nullptr;
   a.vwords = (int32_t)cdiv(slots, 32);
   a.rec = (int4*)(base + lay.rec);
@@ -362,27 +370,30 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   sr->pgrid = persistent_grid(r, sr->parent);
   // the thresholded children's kernel walks the lists of the parent kernel's
   // workgroups: one grid for both, all of it resident in either
-  if (sr->third && !hint) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
+  if (sr->third && !bfs) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
   sr->cgrid = sr->child ? persistent_grid(r, sr->child) : 0;
   // the harvest: as many workgroups as its rounds need, at most the parent
   // grid (a small graph's many narrow levels launch it empty)
-  sr->tgrid = !sr->third ? 0
-              : !hint    ? sr->pgrid
-                         : (int)std::min<int64_t>(sr->pgrid, cdiv(slots, (int64_t)PB * HARVEST_RUNS));
+  const int hgrid = (int)std::min<int64_t>(sr->pgrid, cdiv(slots, (int64_t)PB * HARVEST_RUNS));
+  sr->tgrid = !sr->third ? 0 : bfs ? hgrid : sr->pgrid;
+  sr->fgrid = sr->fourth ? hgrid : 0;
   sr->steps = o.steps_per_replay ? o.steps_per_replay : kDefaultSteps;
   sr->stream = (hipStream_t)stream;
   if (tm) {
     sr->parent = parent_kernel_ptr(problem, gran, true);
-    sr->child = sr->child ? child_kernel_ptr(problem, true, hint) : nullptr;
-    sr->third = hint ? harvest_kernel_ptr(true) : serial_kernel_ptr(problem, gran, true);
+    sr->child = sr->child ? child_kernel_ptr(problem, true, bfs && hint) : nullptr;
+    sr->third = bfs ? (hint ? harvest_kernel_ptr(problem, true) : nullptr)
+                    : serial_kernel_ptr(problem, gran, true);
+    sr->fourth = !bfs && hint ? harvest_kernel_ptr(problem, true) : nullptr;
     // a timed kernel that needs more registers than its product one runs on
     // the grid that is resident at its own occupancy (a larger grid would run
     // in two rounds and time the second round's wait as work)
     sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->parent));
-    if (sr->third && !hint) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
+    if (sr->third && !bfs) sr->pgrid = std::min(sr->pgrid, persistent_grid(r, sr->third));
     if (sr->child) sr->cgrid = std::min(sr->cgrid, persistent_grid(r, sr->child));
-    sr->tgrid = !sr->third ? 0 : !hint ? sr->pgrid
+    sr->tgrid = !sr->third ? 0 : !bfs ? sr->pgrid
                 : std::min(sr->tgrid, persistent_grid(r, sr->third));
+    if (sr->fourth) sr->fgrid = std::min(sr->fgrid, persistent_grid(r, sr->fourth));
     a.tm = tm;
   }
   return DPO_OK;
@@ -468,7 +479,8 @@ dpo_status replay(Runtime& r, SetRun& sr, hipGraphExec_t exec) {
 dpo_status run_to_completion(Runtime& r, SetRun& sr, int64_t max_levels) {
   hipGraphExec_t exec;
   dpo_status s =
-      get_exec(r, sr.parent, sr.child, sr.third, sr.pgrid, sr.cgrid, sr.tgrid, sr.steps, sr.a, &exec);
+      get_exec(r, sr.parent, sr.child, sr.third, sr.fourth, sr.pgrid, sr.cgrid, sr.tgrid, sr.fgrid,
+               sr.steps, sr.a, &exec);
   if (s != DPO_OK) return s;
   const int64_t max_replays = max_levels / sr.steps + 2;
   for (int64_t rep = 0; rep < max_replays; ++rep) {
@@ -632,6 +644,9 @@ dpo_status launch_step(SetRun& sr, uint32_t step) {
     return DPO_ERR_HIP;
   if (sr.third &&
       hipLaunchKernel(sr.third, dim3((unsigned)sr.tgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
+    return DPO_ERR_HIP;
+  if (sr.fourth &&
+      hipLaunchKernel(sr.fourth, dim3((unsigned)sr.fgrid), dim3(PB), p, 0, sr.stream) != hipSuccess)
     return DPO_ERR_HIP;
   return DPO_OK;
 }
@@ -893,8 +908,8 @@ dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_opt
     e->hq = (Query*)((char*)p + 64);
     e->hlist = (int32_t*)(e->hq + max_queries);
     std::memset(e->hq, 0, (size_t)max_queries * sizeof(Query));
-    s = get_exec(r, e->sr.parent, e->sr.child, e->sr.third, e->sr.pgrid, e->sr.cgrid,
-                 e->sr.tgrid, e->sr.steps, e->sr.a, &e->exec, false);
+    s = get_exec(r, e->sr.parent, e->sr.child, e->sr.third, e->sr.fourth, e->sr.pgrid,
+                 e->sr.cgrid, e->sr.tgrid, e->sr.fgrid, e->sr.steps, e->sr.a, &e->exec, false);
   }
   if (s == DPO_OK) s = start_set(r, e->sr);
   if (s == DPO_OK && e->sr.a.hint) {

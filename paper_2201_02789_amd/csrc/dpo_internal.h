@@ -40,10 +40,9 @@ enum { S_FRONT = 0, S_SERIAL, S_REC, S_CHILD, S_ESER, S_ECHILD, S_DESC };
 //   workgroup's waves), [7] the largest total of one wave.
 // Rows of levels >= TM_LEVELS are not written.
 constexpr int TM_LEVELS = 64;
-constexpr int TM_KINDS = 3;  // parent kernel, child kernel, third kernel of the level step
+constexpr int TM_KINDS = 4;  // parent kernel, child kernel, thresholded children, harvest
 constexpr int TM_ROW = 8;
-// the third kernel: SSSP's thresholded children, BFS's harvest (same row kind)
-enum { TK_PARENT = 0, TK_CHILD = 1, TK_SERIAL = 2, TK_HARVEST = 2 };
+enum { TK_PARENT = 0, TK_CHILD = 1, TK_SERIAL = 2, TK_HARVEST = 3 };
 enum { TP_PARENT = 0, TP_AGG, TP_LAUNCH, TP_DISAGG, TP_CHILD, TP_N };
 
 // Counters of one level; three sets rotate by level % 3 so that the parent
@@ -99,8 +98,9 @@ struct Args {
   int32_t* front1;
   uint32_t* visit;                 // BFS: two bitmaps of vwords words, then NHINT per-XCD
                                    // copies; SSSP: stamps [slots]
-  uint8_t* found;                  // BFS with per-XCD copies: [vwords * 32] bytes, set for
-                                   // the vertices a wide level's child bodies find
+  uint8_t* found;                  // [vwords * 32] bytes (Args::hint), set for the vertices
+                                   // a level's child bodies find (BFS: wide levels) or
+                                   // improve (SSSP); read by the harvest kernel
   int4* rec;                       // [slots] launch records {row start, deg, offset, parent dist}
   int32_t* rec_q;                  // [slots] query of each record
   int32_t* rec_slot;               // [slots] SSSP: slot of each record's parent
@@ -129,10 +129,12 @@ struct Args {
                                    // (1) or each in its parent's lane (0)
   int32_t dyn_pct;                 // child kernel: percent of each XCD group's blocks
                                    // that its waves claim in chunks (0 = even split)
-  int32_t hint;                    // BFS: per-XCD visited copies in use on wide levels
-                                   // (probed by the XCD's workgroups, at visit + (2 + x) *
-                                   // vwords, x = XCD), discoveries recorded in `found` and
-                                   // taken into bitmap 0 by the harvest kernel
+  int32_t hint;                    // found bytes and the harvest kernel in use.  BFS:
+                                   // per-XCD visited copies on wide levels (probed by the
+                                   // XCD's workgroups, at visit + (2 + x) * vwords, x =
+                                   // XCD), discoveries taken into bitmap 0 by the harvest;
+                                   // SSSP: improvements queued by the harvest instead of
+                                   // iteration stamps
 };
 
 // timed: the instantiation that stamps its phases into Args::tm
@@ -141,7 +143,7 @@ const void* parent_kernel_ptr(int problem, int gran, bool timed = false);
 // per-XCD copies, Args::hint)
 const void* child_kernel_ptr(int problem, bool timed = false, bool nt = false);
 const void* serial_kernel_ptr(int problem, int gran, bool timed = false);
-const void* harvest_kernel_ptr(bool timed = false);
+const void* harvest_kernel_ptr(int problem, bool timed = false);
 const void* init_kernel_ptr(int problem);
 const void* admit_kernel_ptr(int problem);
 const void* admit_sources_kernel_ptr();

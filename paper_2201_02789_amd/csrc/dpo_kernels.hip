@@ -43,8 +43,9 @@
 // Child body: BFS probes a visited bitmap (one bit per output slot,
 // L2-resident), claims v in a second bitmap and writes its level; SSSP relaxes
 // a second distance array with atomicMin and queues v once per iteration
-// through an iteration stamp.  The probed and the updated copies swap every
-// level.  BFS single traversals and the serving engine instead give each XCD a
+// through an iteration stamp, or, for single traversals and the serving
+// engine, records v as found and leaves the queueing to the harvest kernel.
+// The probed and the updated copies swap every level.  BFS single traversals and the serving engine instead give each XCD a
 // probed copy of its own on wide levels and record discoveries as bytes, which
 // a third kernel, the harvest, turns into levels and the next frontier (Vis,
 // vis_of, harvest_kernel).
@@ -342,6 +343,15 @@ __device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const
     for (int u = 0; u < U; ++u) {
       if (sl[u] >= 0 && nd[u] < cur[u]) cur[u] = atomicMin(&dl[sl[u]], nd[u]);
       else cur[u] = 0u;
+    }
+    // Found bytes (Args::hint): an improved vertex is recorded with a plain
+    // byte store and queued once by the harvest kernel after the level, so an
+    // improving lane waits for no atomic after its atomicMin.
+    if (a.hint) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (nd[u] < cur[u]) a.found[sl[u]] = 1;
+      return;
     }
     const uint32_t it = L + 1;
     uint32_t stamp[U];
@@ -1288,8 +1298,10 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
 }
 
 // ------------------------------------------------------------ harvest kernel
-// BFS with per-XCD copies, after a wide level's child kernel: a found vertex
-// that bitmap 0 lacks was discovered at this level.  It gets its level, its
+// The last kernel of a level step with found bytes (Args::hint).  SSSP: every
+// found vertex was improved at this level; it joins the next frontier once and
+// its byte is cleared for the next level.  BFS with per-XCD copies, after a
+// wide level: a found vertex that bitmap 0 lacks was discovered at this level.  It gets its level, its
 // bit in bitmap 0 and a place in the next frontier (in slot order, which also
 // makes the next level's row loads mostly consecutive).  One lane per slot: a
 // run of 64 slots is 64 found bytes and the two bitmap words they map to, which
@@ -1299,7 +1311,7 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
 // and a serving engine clears all of them when it is created
 // (clear_found_kernel), so slots outside every admitted query hold none.  A
 // narrow level claimed and appended in place, and its harvest returns at once.
-template <bool TM>
+template <int P, bool TM>
 __global__ __launch_bounds__(PB) void harvest_kernel(Args a, uint32_t step) {
   __shared__ int32_t s_stage[NW][STAGE];
   __shared__ uint32_t s_bc[NW + 8];
@@ -1313,13 +1325,13 @@ __global__ __launch_bounds__(PB) void harvest_kernel(Args a, uint32_t step) {
   if (st->done || st->error) return;
   const uint32_t L = st->base + step;
   LevelSet* cur = &st->set[L % 3];
-  if (!(cur->vmode & 2u)) return;
+  if (P == PROB_BFS && !(cur->vmode & 2u)) return;
   int32_t* fout = (L & 1) ? a.front0 : a.front1;
   Stage s{s_stage[wave], 0u};
   const uint32_t n = (uint32_t)a.slots;
-  // a single traversal has one level value; with several queries it is looked
-  // up per found vertex
-  const int32_t lv1 = (int32_t)(L + 1) - a.q[0].lstart;
+  // BFS: a single traversal has one level value; with several queries it is
+  // looked up per found vertex
+  const int32_t lv1 = P == PROB_BFS ? (int32_t)(L + 1) - a.q[0].lstart : 0;
   // HU runs of 64 slots per wave and round, all their loads issued first
   constexpr int HU = HARVEST_RUNS;
   for (uint32_t b = (blockIdx.x * NW + wave) * (64u * HU); b < n; b += gridDim.x * PB * HU) {
@@ -1328,12 +1340,17 @@ __global__ __launch_bounds__(PB) void harvest_kernel(Args a, uint32_t step) {
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
       const uint32_t v = b + (uint32_t)k * 64u + (uint32_t)lane;
-      c[k] = v < n ? a.visit[v >> 5] : ~0u;
+      c[k] = (P == PROB_BFS && v < n) ? a.visit[v >> 5] : 0u;
       f[k] = v < n && a.found[v] != 0;
     }
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
       const uint32_t v = b + (uint32_t)k * 64u + (uint32_t)lane;
+      if (P == PROB_SSSP) {
+        if (f[k]) a.found[v] = 0;
+        stage_push(s, f[k], (int32_t)v, a, cur, fout, lane);
+        continue;
+      }
       const bool nw = f[k] && !((c[k] >> (v & 31)) & 1u);
       const unsigned long long m = __ballot(nw);
       if (m) {  // wave-uniform
@@ -1398,7 +1415,7 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
       const uint32_t d = (v == src) ? 0u : 0xFFFFFFFFu;
       a.dist[s0 + v] = d;
       a.dist2[s0 + v] = d;
-      a.visit[s0 + v] = 0u;
+      if (!a.hint) a.visit[s0 + v] = 0u;  // iteration stamps
     }
   }
   const uint32_t words = ((uint32_t)Q.n + 31) / 32;
@@ -1413,6 +1430,9 @@ __global__ __launch_bounds__(PB) void admit_kernel(Args a, const int32_t* list, 
         uint32_t* f = (uint32_t*)(a.found + (size_t)(s0 / 32 + i) * 32);
         for (int k = 0; k < 8; ++k) f[k] = 0u;
       }
+    } else if (a.hint) {  // SSSP: nothing found yet
+      uint32_t* f = (uint32_t*)(a.found + (size_t)(s0 / 32 + i) * 32);
+      for (int k = 0; k < 8; ++k) f[k] = 0u;
     }
   }
   if (reset) {
@@ -1491,8 +1511,12 @@ const void* serial_kernel_ptr(int problem, int gran, bool timed) {
                : parent_for<PROB_SSSP, PH_SERIAL, false>(gran);
 }
 
-const void* harvest_kernel_ptr(bool timed) {
-  return timed ? (const void*)harvest_kernel<true> : (const void*)harvest_kernel<false>;
+const void* harvest_kernel_ptr(int problem, bool timed) {
+  if (problem == PROB_BFS)
+    return timed ? (const void*)harvest_kernel<PROB_BFS, true>
+                 : (const void*)harvest_kernel<PROB_BFS, false>;
+  return timed ? (const void*)harvest_kernel<PROB_SSSP, true>
+               : (const void*)harvest_kernel<PROB_SSSP, false>;
 }
 
 template <bool TM>

@@ -273,7 +273,7 @@ def dpo_bfs_noalloc(graph: DeviceGraph, source: int, opts: Options, levels, stre
         raise DpoError(rc, "dpo_bfs_noalloc")
 
 
-TIMING_BYTES = 64 * 3 * 4096 * 8 * 8  # DPO_TIMING_BYTES
+TIMING_BYTES = 64 * 4 * 4096 * 8 * 8  # DPO_TIMING_BYTES
 TIMING_PHASES = ("parent", "aggregation", "launch", "disaggregation", "child")
 
 

@@ -48,7 +48,7 @@ def test_timed_traversal_matches_and_rows_are_well_formed(s16, kind, opts):
     torch.cuda.synchronize()
     got = out.cpu().numpy() if kind == "bfs" else dpo.as_uint32(out)
     assert np.array_equal(got, want), (kind, opts.label())
-    rows = timing.cpu().numpy().view(np.uint64).reshape(64, 3, 4096, 8)
+    rows = timing.cpu().numpy().view(np.uint64).reshape(64, 4, 4096, 8)
     ran = rows[:, :, :, 1] != 0
     levels = int(want.max()) + 1 if kind == "bfs" else None
     # every level with a frontier ran its parent kernel; rows only where kernels ran
