@@ -61,36 +61,56 @@ def test_certify_rejects_planted_mistakes():
 def test_phase_split_on_known_rows():
     """Two levels of hand-made timing rows (100 ticks = 1 us): each kernel's
     span is split by its cycle shares, the parent-to-child gap is launch time,
-    the gap into the next level is a gap, workgroups that did not run (zero
-    rows) are ignored."""
-    rows = np.zeros((64, 3, 4096, 8), dtype=np.uint64)
+    the gaps into the harvest and into the next level are gaps, workgroups that
+    did not run (zero rows) are ignored."""
+    rows = np.zeros((64, 4, 4096, 8), dtype=np.uint64)
 
     def put(L, k, wg, t0, t1, cyc):
         rows[L, k, wg, 0], rows[L, k, wg, 1] = t0, t1
         rows[L, k, wg, 2:7] = cyc
 
-    # level 0: parent kernel 0..100 (two workgroups), child kernel 120..320
+    # level 0: parent kernel 0..100 (two workgroups), child kernel 120..320,
+    # harvest 330..340 (its cycles are child work)
     put(0, 0, 0, 0, 100, [30, 15, 5, 0, 0])
     put(0, 0, 7, 10, 90, [30, 15, 5, 0, 0])
     put(0, 1, 0, 120, 320, [0, 0, 0, 10, 90])
     put(0, 1, 3, 130, 220, [0, 0, 0, 10, 90])
-    # level 1 starts 30 ticks after level 0 ends: parent only (no launches)
+    put(0, 3, 2, 330, 340, [0, 0, 0, 0, 10])
+    # level 1 starts 10 ticks after level 0 ends: parent only (no launches)
     put(1, 0, 0, 350, 450, [100, 0, 0, 0, 0])
     tot, per_level, imb = bench.phase_split(rows)
     want = {"parent": 0.6 + 1.0, "aggregation": 0.3, "launch": 0.1 + 0.2,
-            "disaggregation": 0.2, "child": 1.8, "gaps": 0.3}
+            "disaggregation": 0.2, "child": 1.8 + 0.1, "gaps": 0.1 + 0.1}
     for k, v in want.items():
         assert abs(tot[k] - v) < 1e-9, (k, tot[k], v)
     assert [L for L, _ in per_level] == [0, 1]
-    assert abs(sum(per_level[0][1].values()) - 3.2) < 1e-9  # 0 .. 320 ticks
+    assert abs(sum(per_level[0][1].values()) - 3.4) < 1e-9  # 0 .. 340 ticks
     # child workgroup spans 200 and 90 ticks: busiest / mean = 200 / 145
     assert abs(imb - 200 / 145) < 1e-9
+
+
+def test_level_table_names_the_four_kernels():
+    """Per level: each kernel's span (first entry to last exit) under its own
+    name, and the child kernel's workgroup statistics."""
+    rows = np.zeros((64, 4, 4096, 8), dtype=np.uint64)
+    rows[0, 0, 0, :2] = (0, 50)
+    rows[0, 1, 0, :2], rows[0, 1, 1, :2] = (60, 160), (70, 110)
+    rows[0, 2, 5, :2] = (170, 200)
+    rows[0, 3, 9, :2] = (210, 220)
+    rows[1, 0, 0, :2] = (300, 320)
+    t = bench.level_table(rows)
+    assert [r["level"] for r in t] == [0, 1]
+    r = t[0]
+    assert (r["parent_us"], r["child_us"], r["serial_us"], r["harvest_us"]) == (0.5, 1.0, 0.3, 0.1)
+    assert (r["child_wg_mean_us"], r["child_wg_max_us"], r["child_workgroups"]) == (0.7, 1.0, 2)
+    assert r["child_exit_spread_us"] == 0.5
+    assert t[1] == {"level": 1, "parent_us": 0.2}
 
 
 def test_child_skew_on_known_rows():
     """Sixteen child workgroups, those on XCD 3 (workgroups 3 and 11) twice as
     long as the others; entries spread over 10 ticks, exits as they fall."""
-    rows = np.zeros((64, 3, 4096, 8), dtype=np.uint64)
+    rows = np.zeros((64, 4, 4096, 8), dtype=np.uint64)
     for w in range(16):
         t0 = 100 + (w % 11)  # entries 100 .. 110
         span = 200 if w % 8 == 3 else 100
