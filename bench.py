@@ -112,7 +112,7 @@ TUNED = {"bfs22": dict(threshold=64, coarsen=1, agg=3, agg_blocks=4, child_block
                         child_block=128, dyn_share=50)}
 
 
-SERVE_T = {"bfs": 64, "sssp": 256}  # thresholds of the serving engines
+SERVE_T = {"bfs": 64, "sssp": 512}  # thresholds of the serving engines
 SERVE_DYN = {"bfs": 0, "sssp": 50}  # percent of child blocks claimed in chunks
 SERVE_CB = {"bfs": 128, "sssp": 128}  # original child block sizes of the serving engines
 
