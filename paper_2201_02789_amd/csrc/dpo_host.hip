@@ -321,7 +321,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
                     (o.claim_hint == DPO_HINT_AUTO && !batch_call && dense);
   const bool bfs = problem == PROB_BFS;
   sr->parent = parent_kernel_ptr(problem, gran);
-  sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem, false, bfs && hint);
+  sr->child = gran == AGG_FLAT ? nullptr : child_kernel_ptr(problem, false, hint);
   sr->third = bfs ? (hint ? harvest_kernel_ptr(problem) : nullptr) : serial_kernel_ptr(problem, gran);
   sr->fourth = !bfs && hint ? harvest_kernel_ptr(problem) : nullptr;
   if (!sr->parent) return DPO_ERR_UNSUPPORTED;
@@ -381,7 +381,7 @@ dpo_status prepare_set(Runtime& r, int problem, const dpo_csr* g, const dpo_opti
   sr->stream = (hipStream_t)stream;
   if (tm) {
     sr->parent = parent_kernel_ptr(problem, gran, true);
-    sr->child = sr->child ? child_kernel_ptr(problem, true, bfs && hint) : nullptr;
+    sr->child = sr->child ? child_kernel_ptr(problem, true, hint) : nullptr;
     sr->third = bfs ? (hint ? harvest_kernel_ptr(problem, true) : nullptr)
                     : serial_kernel_ptr(problem, gran, true);
     sr->fourth = !bfs && hint ? harvest_kernel_ptr(problem, true) : nullptr;

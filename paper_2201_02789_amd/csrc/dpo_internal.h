@@ -139,8 +139,8 @@ struct Args {
 
 // timed: the instantiation that stamps its phases into Args::tm
 const void* parent_kernel_ptr(int problem, int gran, bool timed = false);
-// nt: the child kernel's adjacency loads are non-temporal (used with the
-// per-XCD copies, Args::hint)
+// nt: the child kernel's adjacency (and weight) loads are non-temporal (used
+// with found bytes, Args::hint)
 const void* child_kernel_ptr(int problem, bool timed = false, bool nt = false);
 const void* serial_kernel_ptr(int problem, int gran, bool timed = false);
 const void* harvest_kernel_ptr(int problem, bool timed = false);

@@ -1239,12 +1239,14 @@ __global__ __launch_bounds__(PB) void child_kernel(Args a, uint32_t step) {
               c[u].lv = __builtin_amdgcn_readlane(win.lv, k);
               c[u].du = (uint32_t)__builtin_amdgcn_readlane((int32_t)win.du, k);
               if (e0 + lane < e1 && !((sup >> k) & 1ull)) {
-                // NT (single traversals with per-XCD copies): the level's
-                // adjacency is read once, so its lines leave L2 first and the
-                // probed bitmaps and found bytes stay.  A batch of many
+                // NT (with found bytes: single traversals, the serving
+                // engine): the level's adjacency (and weights) are read once,
+                // so their lines leave L2 first and the probed bitmaps or
+                // distances and the found bytes stay.  A batch of many
                 // traversals over few graphs reads each adjacency again.
                 v[u] = NT ? __builtin_nontemporal_load(&a.col[e0 + lane]) : a.col[e0 + lane];
-                if (P == PROB_SSSP) w[u] = a.w[e0 + lane];
+                if (P == PROB_SSSP)
+                  w[u] = NT ? __builtin_nontemporal_load(&a.w[e0 + lane]) : a.w[e0 + lane];
               }
             }
           }
@@ -1524,7 +1526,8 @@ static const void* child_ptr(int problem, bool nt) {
   if (problem == PROB_BFS)
     return nt ? (const void*)child_kernel<PROB_BFS, TM, true>
               : (const void*)child_kernel<PROB_BFS, TM, false>;
-  return (const void*)child_kernel<PROB_SSSP, TM, false>;
+  return nt ? (const void*)child_kernel<PROB_SSSP, TM, true>
+            : (const void*)child_kernel<PROB_SSSP, TM, false>;
 }
 
 const void* child_kernel_ptr(int problem, bool timed, bool nt) {
