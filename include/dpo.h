@@ -314,7 +314,9 @@ size_t dpo_engine_workspace_bytes(const dpo_options* o, int32_t max_queries, int
  * running queries (the footprint pool).  ws: device, dpo_engine_workspace_bytes;
  * out_arena: device int32/uint32[round_up(max_slots, 32)] engine-owned
  * scratch for running queries' outputs.  The arena, ws and out_arena must
- * outlive the engine.  The engine keeps a copy of graph_vbase. */
+ * outlive the engine; ws may hold anything (the call initialises what the
+ * kernels read before any admission, on `stream`, and waits for it).  The
+ * engine keeps a copy of graph_vbase. */
 dpo_status dpo_engine_create(const dpo_arena* arena, int32_t kind, const dpo_options* bucket_opts,
                              int32_t nbuckets, const int32_t* graph_bucket, int32_t max_queries,
                              int64_t max_slots, void* ws, size_t ws_bytes, void* out_arena,
