@@ -2,7 +2,8 @@
 //
 // Each level is two kernels, the parent kernel and the child kernel; for SSSP
 // the parent kernel's second pass (the thresholded children) runs as a third
-// kernel after the child kernel.
+// kernel after the child kernel, and with found bytes (single traversals, the
+// serving engine) a harvest kernel ends the level.
 //
 // Parent kernel: the parent grid.  Workgroups (256 lanes = 4 wave64) take
 // virtual parent blocks of 256 frontier entries in a grid-stride loop; lane i
@@ -241,10 +242,11 @@ __device__ __forceinline__ uint32_t coherent_load(const uint32_t* p) {
 
 // Child body for U neighbours per lane (v < 0: none), all probes issued before
 // any atomic so that the U round trips overlap.  BFS: probe, then claim the
-// unvisited ones and write their level.  SSSP: relax (atomicMin) the edges
-// that improve on the probed distance; an improved vertex joins the next
-// frontier once per level (iteration stamp exchanged atomically).  out[u] is
-// the slot to append to the next frontier, or -1.
+// unvisited ones and write their level (per-XCD copies: record them as found).
+// SSSP: relax (atomicMin) the edges that improve on the probed distance; an
+// improved vertex joins the next frontier once per level (iteration stamp
+// exchanged atomically, or a found byte that the harvest kernel reads).
+// out[u] is the slot to append to the next frontier, or -1.
 template <int P, int U>
 __device__ __forceinline__ void visit_batch(const Args& a, const Vis& vis, const int32_t (&v)[U],
                                             const uint32_t (&w)[U], const Elem (&c)[U],
@@ -557,9 +559,9 @@ __global__ __launch_bounds__(PB) void parent_kernel(Args a, uint32_t step) {
     return;
   }
   // Each vertex enters a frontier at most once per level (the claim atomic,
-  // the SSSP stamp), and the launch records, serial lists and group counters
-  // of a level are sized for that; a larger frontier is an error, never an
-  // index past them.
+  // the SSSP stamp, the harvest of found bytes), and the launch records,
+  // serial lists and group counters of a level are sized for that; a larger
+  // frontier is an error, never an index past them.
   if (F > (uint32_t)a.slots) {
     if (tid == 0) set_error(st, ERR_CAPACITY);
     return;
